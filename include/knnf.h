@@ -1,0 +1,185 @@
+/*
+ * knnf.h -- C-ABI of the MI355X (gfx950) KNN filtering library.
+ *
+ * The library implements the spatial stage of the spatial-spectral classifier
+ * of Lazcano et al. (Sec. II.C.3 and Fig. 2): given the one-band image I (the
+ * first principal component, "PCA band") and the per-pixel class-probability
+ * maps P of the pixel-wise classifier, it finds each pixel's K nearest
+ * neighbours inside a search window and averages their probabilities.
+ *
+ *   Feature of pixel (r, c):   (I[r][c], lambda*r, lambda*c)      Sec. II.C.3
+ *   Distance (Eq. 1):          squared Euclidean distance of the features,
+ *                              evaluated in IEEE binary32 as
+ *                                fr(x) = fl32(lambda * (float)x)
+ *                                a = fl32(fr(r) - fr(i)), b = fl32(fr(c) - fr(j))
+ *                                e = fl32(I[r][c] - I[i][j])
+ *                                d = fmaf(e, e, fmaf(b, b, fl32(a * a)))
+ *                              (the equation's column term is (c - j)^2; the
+ *                              printed (r - j)^2 contradicts the definitions
+ *                              under it)
+ *   Window (Sec. III.A.3):     rows max(0, r-R) .. min(H-1, r+R), all columns,
+ *                              clipped at the frame edges, the pixel included
+ *   Neighbours:                the K smallest candidates in the strict order
+ *                              (d, then linear index i*W + j), ascending
+ *   Filtered maps (Eq. 2):     S_c = sum of the neighbours' P[.][c] in that
+ *                              order from +0 in binary32; O_c = fl32(S_c / K)
+ *   Class map (Sec. III.A.3.b): the class with the largest S_c; ties go to the
+ *                              lowest class index
+ *
+ * Memory layout (all device memory, owned by the caller, row-major):
+ *   pc1       float [H][W]
+ *   prob      float [H][W][C]   (class index fastest)
+ *   out_prob  float [H][W][C]
+ *   out_class int32 [H][W]
+ *   out_nbr   int32 [H][W][K]   optional (NULL to skip); linear indices i*W+j
+ *   out_dist  float [H][W][K]   optional (NULL to skip)
+ * Output buffers must not overlap the inputs or each other.
+ *
+ * Streams: every filtering call is asynchronous on the given HIP stream
+ * (hipStream_t passed as void*, NULL = the null stream).  Inputs must stay valid
+ * and outputs untouched until the stream has reached the call.  Parameter
+ * validation is synchronous and happens before anything is enqueued.
+ *
+ * Errors: functions return a knnf_status.  KNNF_EINVAL leaves the context
+ * usable.  A HIP launch failure returns KNNF_EDEVICE.  knnf_last_error() gives
+ * a text description of the last failure on the calling thread.
+ *
+ * Inputs are expected to be finite.  Non-finite values do not make the library
+ * read or write out of bounds, but the selected neighbours are then
+ * unspecified.
+ */
+#ifndef KNNF_H
+#define KNNF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KNNF_OK = 0,
+    KNNF_EINVAL = -1,  /* bad parameter or pointer; nothing was enqueued     */
+    KNNF_ENOMEM = -2,  /* a device or host allocation failed                 */
+    KNNF_EDEVICE = -3, /* a HIP call failed                                  */
+    KNNF_EAGAIN = -4,  /* serving queue full; retry later                    */
+    KNNF_ESTATE = -5   /* call not valid in the object's current state       */
+} knnf_status;
+
+/* Parameter limits checked by every filtering call. */
+#define KNNF_MAX_K 64
+#define KNNF_MAX_C 16
+
+/*
+ * One frame: sizes, filter parameters and device pointers.
+ *   H, W    >= 1, H*W <= 2^31 - 1
+ *   C       number of classes, 1..KNNF_MAX_C          (Sec. II.C.1, Eq. 2)
+ *   K       neighbours, 1..KNNF_MAX_K and no larger than the smallest window,
+ *           min(H, R+1) * W (the paper leaves K > window size undefined)
+ *   R       window half-height in rows, >= 0         (Sec. III.A.3)
+ *   lambda  spatial weight, finite, >= 0, lambda * max(H, W) <= 1e18
+ *           (Sec. II.C.3: 0 ignores the coordinates)
+ */
+typedef struct {
+    int32_t H, W, C, K, R;
+    float lambda;
+    const float* pc1;
+    const float* prob;
+    float* out_prob;
+    int32_t* out_class;
+    int32_t* out_nbr;
+    float* out_dist;
+} knnf_frame;
+
+/* Opaque library context: device, workspace for batch tables, tuned plans. */
+typedef struct knnf_ctx knnf_ctx;
+
+/*
+ * Search strategy.
+ *   KNNF_SEARCH_EXHAUSTIVE  evaluates Eq. 1 for every candidate of every window.
+ *   KNNF_SEARCH_PRUNED      skips candidate rows and column chunks whose
+ *                           spatial part of Eq. 1 alone already exceeds the
+ *                           current K-th distance.  Since every term of Eq. 1
+ *                           is non-negative and binary32 rounding is monotone,
+ *                           the skipped candidates could never be selected:
+ *                           the outputs are bit-identical to the exhaustive
+ *                           search.
+ */
+typedef enum { KNNF_SEARCH_EXHAUSTIVE = 0, KNNF_SEARCH_PRUNED = 1 } knnf_search;
+
+/*
+ * Launch plan: how a frame is cut into work.
+ *   search        one of knnf_search
+ *   queries       pixels per wavefront task (a vertical strip); 4, 8 or 16
+ *   waves         wavefronts per workgroup; 1, 2 or 4
+ * A zero field means "library default / tuned value".
+ */
+typedef struct {
+    int32_t search;
+    int32_t queries;
+    int32_t waves;
+    int32_t reserved;
+} knnf_plan;
+
+/* Create a context on HIP device `device` (ordinal).  *out is NULL on error. */
+knnf_status knnf_create(knnf_ctx** out, int device);
+
+/* Free the context and its device workspace.  NULL is accepted. */
+knnf_status knnf_destroy(knnf_ctx* ctx);
+
+/* Default plan used when a call passes no plan (NULL).  Validated. */
+knnf_status knnf_set_default_plan(knnf_ctx* ctx, const knnf_plan* plan);
+knnf_status knnf_get_default_plan(const knnf_ctx* ctx, knnf_plan* plan);
+
+/*
+ * Check a frame's sizes, parameters and pointers without launching anything.
+ * Returns KNNF_OK or KNNF_EINVAL.
+ */
+knnf_status knnf_validate(const knnf_frame* frame);
+
+/*
+ * Filter one frame (Sec. II.C.3, Eq. 1 and 2) with one kernel launch on
+ * `stream`.  plan may be NULL.
+ */
+knnf_status knnf_filter(knnf_ctx* ctx, const knnf_frame* frame,
+                        const knnf_plan* plan, void* stream);
+
+/*
+ * Filter n frames of possibly different sizes and parameters with one
+ * persistent launch on `stream`: workgroups pull per-wavefront tasks from a
+ * shared counter, largest frames first.  Every frame's outputs are bitwise
+ * equal to knnf_filter() of that frame alone.  The frame table is copied to
+ * the context's device workspace with an asynchronous copy on `stream`; the
+ * caller's array may be reused when the call returns.  Calls on one context
+ * must not run concurrently from several host threads.
+ */
+knnf_status knnf_filter_batch(knnf_ctx* ctx, const knnf_frame* frames, int n,
+                              const knnf_plan* plan, void* stream);
+
+/*
+ * Autotuner: time each candidate plan on the given frames (device buffers of
+ * the caller; their outputs are overwritten) and keep the fastest per shape
+ * bucket.  `reps` timed repetitions per plan (>= 1).  Synchronises the stream.
+ * The chosen plan for the frame set is written to *best when best != NULL.
+ */
+knnf_status knnf_tune(knnf_ctx* ctx, const knnf_frame* frames, int n, int reps,
+                      void* stream, knnf_plan* best);
+
+/*
+ * Bytes of device memory a frame occupies (inputs + outputs, each buffer
+ * rounded up to 256 bytes), used to admit frames into a fixed pool.
+ */
+size_t knnf_frame_bytes(int H, int W, int C, int K, int with_nbr);
+
+/* Text of the last error on the calling thread ("" if none). */
+const char* knnf_last_error(void);
+
+/* Library version, e.g. "knnf 0.1.0 gfx950". */
+const char* knnf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KNNF_H */

@@ -1,0 +1,15 @@
+"""Test configuration: the ``gpu`` marker and import paths.
+
+Tests marked ``gpu`` need an AMD Instinct GPU (gfx950) and the built HIP
+library; everything else runs on the CPU.
+"""
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
