@@ -1,0 +1,169 @@
+"""ctypes binding of ``libknnf.so`` (the C-ABI declared in include/knnf.h).
+
+Argument marshalling only: every step of the filter runs in the HIP kernels.
+The functions keep the C names (``knnf_create``, ``knnf_filter``, ...).  Device
+buffers are passed as integer addresses (``tensor.data_ptr()``) and streams as
+integer handles (``torch.cuda.current_stream().cuda_stream``).
+
+The library is loaded after torch so that both use the one HIP runtime
+(torch's ``libamdhip64.so`` carries the same SONAME the library links against).
+If ``libknnf.so`` is missing the import fails loudly: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libknnf.so")
+
+KNNF_OK = 0
+KNNF_EINVAL = -1
+KNNF_ENOMEM = -2
+KNNF_EDEVICE = -3
+KNNF_EAGAIN = -4
+KNNF_ESTATE = -5
+
+KNNF_SEARCH_EXHAUSTIVE = 0
+KNNF_SEARCH_PRUNED = 1
+
+KNNF_MAX_K = 64
+KNNF_MAX_C = 16
+
+_STATUS_NAMES = {0: "KNNF_OK", -1: "KNNF_EINVAL", -2: "KNNF_ENOMEM", -3: "KNNF_EDEVICE",
+                 -4: "KNNF_EAGAIN", -5: "KNNF_ESTATE"}
+
+
+class knnf_frame(ctypes.Structure):
+    _fields_ = [
+        ("H", ctypes.c_int32), ("W", ctypes.c_int32), ("C", ctypes.c_int32),
+        ("K", ctypes.c_int32), ("R", ctypes.c_int32), ("lam", ctypes.c_float),
+        ("pc1", ctypes.c_void_p), ("prob", ctypes.c_void_p),
+        ("out_prob", ctypes.c_void_p), ("out_class", ctypes.c_void_p),
+        ("out_nbr", ctypes.c_void_p), ("out_dist", ctypes.c_void_p),
+    ]
+
+
+class knnf_plan(ctypes.Structure):
+    _fields_ = [("search", ctypes.c_int32), ("queries", ctypes.c_int32),
+                ("waves", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"search": self.search, "queries": self.queries, "waves": self.waves}
+
+
+class KnnfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+# Every symbol include/knnf.h declares, with its ctypes signature.
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_SIGS = {
+    "knnf_create": (_I, [ctypes.POINTER(_P), _I]),
+    "knnf_destroy": (_I, [_P]),
+    "knnf_set_default_plan": (_I, [_P, ctypes.POINTER(knnf_plan)]),
+    "knnf_get_default_plan": (_I, [_P, ctypes.POINTER(knnf_plan)]),
+    "knnf_validate": (_I, [ctypes.POINTER(knnf_frame)]),
+    "knnf_filter": (_I, [_P, ctypes.POINTER(knnf_frame), ctypes.POINTER(knnf_plan), _P]),
+    "knnf_filter_batch": (_I, [_P, ctypes.POINTER(knnf_frame), _I, ctypes.POINTER(knnf_plan), _P]),
+    "knnf_tune": (_I, [_P, ctypes.POINTER(knnf_frame), _I, _I, _P, ctypes.POINTER(knnf_plan)]),
+    "knnf_frame_bytes": (ctypes.c_size_t, [_I, _I, _I, _I, _I]),
+    "knnf_last_error": (ctypes.c_char_p, []),
+    "knnf_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load():
+    """Load libknnf.so (after torch) and set the signatures.  Raises if unbuilt."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  -- the HIP runtime torch uses must be loaded first
+
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                           "or python -m paper_2404_10631_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return sorted(_SIGS)
+
+
+def last_error() -> str:
+    return load().knnf_last_error().decode()
+
+
+def check(status: int) -> None:
+    if status != KNNF_OK:
+        raise KnnfError(status, last_error())
+
+
+def _plan_ptr(plan):
+    if plan is None:
+        return None
+    if isinstance(plan, dict):
+        p = knnf_plan(int(plan.get("search", 0)), int(plan.get("queries", 0)),
+                      int(plan.get("waves", 0)), 0)
+    else:
+        p = plan
+    return ctypes.byref(p)
+
+
+def knnf_version() -> str:
+    return load().knnf_version().decode()
+
+
+def knnf_create(device: int = 0) -> int:
+    h = ctypes.c_void_p()
+    check(load().knnf_create(ctypes.byref(h), int(device)))
+    return h.value
+
+
+def knnf_destroy(ctx: int) -> None:
+    check(load().knnf_destroy(ctx))
+
+
+def knnf_set_default_plan(ctx: int, plan) -> None:
+    check(load().knnf_set_default_plan(ctx, _plan_ptr(plan)))
+
+
+def knnf_get_default_plan(ctx: int) -> knnf_plan:
+    p = knnf_plan()
+    check(load().knnf_get_default_plan(ctx, ctypes.byref(p)))
+    return p
+
+
+def knnf_validate(frame: knnf_frame) -> int:
+    return int(load().knnf_validate(ctypes.byref(frame)))
+
+
+def knnf_filter(ctx: int, frame: knnf_frame, plan=None, stream: int = 0) -> None:
+    check(load().knnf_filter(ctx, ctypes.byref(frame), _plan_ptr(plan), stream))
+
+
+def knnf_filter_batch(ctx: int, frames, plan=None, stream: int = 0) -> None:
+    arr = (knnf_frame * len(frames))(*frames)
+    check(load().knnf_filter_batch(ctx, arr, len(frames), _plan_ptr(plan), stream))
+
+
+def knnf_tune(ctx: int, frames, reps: int = 3, stream: int = 0) -> knnf_plan:
+    arr = (knnf_frame * len(frames))(*frames)
+    best = knnf_plan()
+    check(load().knnf_tune(ctx, arr, len(frames), int(reps), stream, ctypes.byref(best)))
+    return best
+
+
+def knnf_frame_bytes(H: int, W: int, C: int, K: int, with_nbr: bool) -> int:
+    return int(load().knnf_frame_bytes(H, W, C, K, 1 if with_nbr else 0))

@@ -1,0 +1,72 @@
+"""Build the HIP library ``libknnf.so`` for gfx950 (in-tree, next to this file).
+
+Usage: ``python -m paper_2404_10631_amd.build`` or ``build()`` from Python.
+
+Flags that matter for the results:
+* ``-ffp-contract=off`` and ``-fno-fast-math``: every ``*``, ``+``, ``-`` in the
+  kernels is one IEEE binary32 operation; the only fused operations are the
+  explicit ``fmaf`` calls of the distance.
+* ``-fhip-fp32-correctly-rounded-divide-sqrt``: the Eq. 2 division is
+  correctly rounded.
+* ``-fno-gpu-flush-denormals-to-zero``: binary32 subnormals are kept.
+* ``-Xclang -target-feature -Xclang -packed-fp32-ops``: no packed FP32
+  instructions are generated.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libknnf.so")
+ROOT = os.path.dirname(HERE)
+
+SOURCES = ["knnf_kernels.hip", "knnf_api.cpp"]
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = os.environ.get("KNNF_OFFLOAD_ARCH", "gfx950")
+
+COMMON_FLAGS = [
+    "-O3", "-std=c++17", "-fPIC",
+    "-ffp-contract=off", "-fno-fast-math",
+    "-Wall", "-Wno-unused-function", "-Wno-unused-result", "-Wno-unused-value",
+    "-I", os.path.join(ROOT, "include"),
+]
+DEVICE_FLAGS = [
+    f"--offload-arch={ARCH}",
+    "-mcode-object-version=5",
+    "-fhip-fp32-correctly-rounded-divide-sqrt",
+    "-fno-gpu-flush-denormals-to-zero",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+]
+
+
+def build(verbose: bool = False, extra: list[str] | None = None) -> str:
+    """Compile every source into ``libknnf.so``; returns its path."""
+    objs = []
+    for src in SOURCES:
+        path = os.path.join(CSRC, src)
+        obj = os.path.join(CSRC, src + ".o")
+        cmd = [HIPCC] + COMMON_FLAGS + (extra or [])
+        if src.endswith(".hip"):
+            cmd += ["-x", "hip"] + DEVICE_FLAGS
+        cmd += ["-c", path, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        objs.append(obj)
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    for o in objs:
+        os.remove(o)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

@@ -1,0 +1,405 @@
+// knnf_api.cpp -- host runtime behind include/knnf.h.
+//
+// Validation, launch planning, the batch work table and the autotuner.  All
+// arithmetic of the method runs in the HIP kernels (knnf_kernels.hip).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/knnf.h"
+#include "knnf_device.h"
+
+namespace knnf {
+int launch_zero_counter(uint32_t* d_counter, void* stream);
+}
+
+namespace {
+
+thread_local std::string g_err;
+
+knnf_status fail(knnf_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+knnf_status hip_fail(hipError_t e, const char* what) {
+    return fail(KNNF_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// One slot of batch tables: device frame table + task prefix + claim counter,
+// and a pinned host staging copy.  `done` is recorded after the launch that
+// uses the slot, so the slot is reused only after that launch has finished.
+struct BatchSlot {
+    void* dev = nullptr;      // [FrameDesc x cap][uint32 x (cap+1)][uint32 counter]
+    void* host = nullptr;     // pinned staging of the same layout
+    size_t cap = 0;           // frames
+    hipEvent_t done = nullptr;
+    bool recorded = false;
+};
+
+size_t slot_bytes(size_t cap) {
+    size_t a = cap * sizeof(knnf::FrameDesc);
+    a = (a + 255) & ~size_t(255);
+    size_t b = (cap + 1) * sizeof(uint32_t);
+    b = (b + 255) & ~size_t(255);
+    return a + b + 256;
+}
+
+constexpr int kSlots = 4;
+
+}  // namespace
+
+struct knnf_ctx {
+    int device = 0;
+    int num_cu = 256;
+    knnf_plan plan{};
+    std::mutex mu;
+    BatchSlot slots[kSlots];
+    int next_slot = 0;
+    // tuned plans: bucket key -> plan
+    std::map<uint64_t, knnf_plan> tuned;
+};
+
+namespace {
+
+knnf_plan default_plan() {
+    knnf_plan p{};
+    p.search = KNNF_SEARCH_EXHAUSTIVE;
+    p.queries = 8;
+    p.waves = 2;
+    return p;
+}
+
+bool plan_ok(const knnf_plan& p) {
+    if (p.search != KNNF_SEARCH_EXHAUSTIVE && p.search != KNNF_SEARCH_PRUNED) return false;
+    if (p.queries != 4 && p.queries != 8 && p.queries != 16) return false;
+    if (p.waves != 1 && p.waves != 2 && p.waves != 4) return false;
+    if (p.queries == 16 && p.waves == 4) return false;
+    return true;
+}
+
+knnf_plan resolve(const knnf_ctx* ctx, const knnf_plan* p) {
+    knnf_plan r = ctx->plan;
+    if (p) {
+        if (p->search) r.search = p->search;
+        if (p->queries) r.queries = p->queries;
+        if (p->waves) r.waves = p->waves;
+    }
+    return r;
+}
+
+knnf::LaunchCfg to_cfg(const knnf_plan& p) {
+    knnf::LaunchCfg c;
+    c.queries = p.queries;
+    c.waves = p.waves;
+    c.pruned = p.search == KNNF_SEARCH_PRUNED ? 1 : 0;
+    return c;
+}
+
+knnf::FrameDesc to_desc(const knnf_frame& f) {
+    knnf::FrameDesc d;
+    d.pc1 = f.pc1;
+    d.prob = f.prob;
+    d.out_prob = f.out_prob;
+    d.out_class = f.out_class;
+    d.out_nbr = f.out_nbr;
+    d.out_dist = f.out_dist;
+    d.H = f.H;
+    d.W = f.W;
+    d.C = f.C;
+    d.K = f.K;
+    d.R = f.R;
+    d.lambda = f.lambda;
+    return d;
+}
+
+knnf_status validate(const knnf_frame* f, int index) {
+    if (!f) return fail(KNNF_EINVAL, "frame %d: NULL frame", index);
+    if (f->H < 1 || f->W < 1)
+        return fail(KNNF_EINVAL, "frame %d: H=%d W=%d must be >= 1", index, f->H, f->W);
+    if ((int64_t)f->H * f->W > 0x7fffffffLL)
+        return fail(KNNF_EINVAL, "frame %d: H*W exceeds 2^31-1", index);
+    if (f->C < 1 || f->C > KNNF_MAX_C)
+        return fail(KNNF_EINVAL, "frame %d: C=%d outside 1..%d", index, f->C, KNNF_MAX_C);
+    if (f->R < 0) return fail(KNNF_EINVAL, "frame %d: R=%d < 0", index, f->R);
+    if (f->K < 1 || f->K > KNNF_MAX_K)
+        return fail(KNNF_EINVAL, "frame %d: K=%d outside 1..%d", index, f->K, KNNF_MAX_K);
+    const int64_t minrows = std::min<int64_t>((int64_t)f->R + 1, f->H);
+    if ((int64_t)f->K > minrows * f->W)
+        return fail(KNNF_EINVAL, "frame %d: K=%d exceeds the smallest window (%lld pixels)",
+                    index, f->K, (long long)(minrows * f->W));
+    if (!std::isfinite(f->lambda) || f->lambda < 0.0f)
+        return fail(KNNF_EINVAL, "frame %d: lambda must be finite and >= 0", index);
+    if ((double)f->lambda * (double)std::max(f->H, f->W) > 1e18)
+        return fail(KNNF_EINVAL, "frame %d: lambda * max(H, W) exceeds 1e18", index);
+    if (!f->pc1 || !f->prob || !f->out_prob || !f->out_class)
+        return fail(KNNF_EINVAL, "frame %d: NULL required pointer", index);
+    return KNNF_OK;
+}
+
+// Relative cost of one strip task of a frame (candidate pairs per strip).
+double task_cost(const knnf_frame& f, int Q) {
+    const double rows = std::min<double>(2.0 * f.R + 1.0, f.H);
+    return (double)Q * rows * (double)f.W;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* knnf_last_error(void) { return g_err.c_str(); }
+
+const char* knnf_version(void) { return "knnf 0.1.0 gfx950"; }
+
+knnf_status knnf_validate(const knnf_frame* frame) { return validate(frame, 0); }
+
+size_t knnf_frame_bytes(int H, int W, int C, int K, int with_nbr) {
+    if (H < 1 || W < 1 || C < 1 || K < 1) return 0;
+    auto r = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t px = (size_t)H * (size_t)W;
+    size_t t = r(px * 4) + r(px * C * 4) + r(px * C * 4) + r(px * 4);
+    if (with_nbr) t += r(px * K * 4) + r(px * K * 4);
+    return t;
+}
+
+knnf_status knnf_create(knnf_ctx** out, int device) {
+    if (!out) return fail(KNNF_EINVAL, "knnf_create: NULL out");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= n) return fail(KNNF_EINVAL, "device %d of %d", device, n);
+    knnf_ctx* c = new (std::nothrow) knnf_ctx;
+    if (!c) return fail(KNNF_ENOMEM, "knnf_create: out of host memory");
+    c->device = device;
+    c->plan = default_plan();
+    int prev = 0;
+    hipGetDevice(&prev);
+    hipSetDevice(device);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->num_cu = prop.multiProcessorCount;
+    for (auto& s : c->slots) {
+        e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            hipSetDevice(prev);
+            knnf_destroy(c);
+            return hip_fail(e, "hipEventCreate");
+        }
+    }
+    hipSetDevice(prev);
+    *out = c;
+    return KNNF_OK;
+}
+
+knnf_status knnf_destroy(knnf_ctx* ctx) {
+    if (!ctx) return KNNF_OK;
+    int prev = 0;
+    hipGetDevice(&prev);
+    hipSetDevice(ctx->device);
+    for (auto& s : ctx->slots) {
+        if (s.done) {
+            if (s.recorded) hipEventSynchronize(s.done);
+            hipEventDestroy(s.done);
+        }
+        if (s.dev) hipFree(s.dev);
+        if (s.host) hipHostFree(s.host);
+    }
+    hipSetDevice(prev);
+    delete ctx;
+    return KNNF_OK;
+}
+
+knnf_status knnf_set_default_plan(knnf_ctx* ctx, const knnf_plan* plan) {
+    if (!ctx || !plan) return fail(KNNF_EINVAL, "knnf_set_default_plan: NULL argument");
+    knnf_plan p = resolve(ctx, plan);
+    if (!plan_ok(p)) return fail(KNNF_EINVAL, "invalid plan");
+    ctx->plan = p;
+    return KNNF_OK;
+}
+
+knnf_status knnf_get_default_plan(const knnf_ctx* ctx, knnf_plan* plan) {
+    if (!ctx || !plan) return fail(KNNF_EINVAL, "knnf_get_default_plan: NULL argument");
+    *plan = ctx->plan;
+    return KNNF_OK;
+}
+
+knnf_status knnf_filter(knnf_ctx* ctx, const knnf_frame* frame, const knnf_plan* plan,
+                        void* stream) {
+    if (!ctx) return fail(KNNF_EINVAL, "knnf_filter: NULL context");
+    knnf_status st = validate(frame, 0);
+    if (st != KNNF_OK) return st;
+    const knnf_plan p = resolve(ctx, plan);
+    if (!plan_ok(p)) return fail(KNNF_EINVAL, "knnf_filter: invalid plan");
+    int prev = 0;
+    hipGetDevice(&prev);
+    if (prev != ctx->device) hipSetDevice(ctx->device);
+    const int e = knnf::launch_filter_frame(to_desc(*frame), to_cfg(p), stream);
+    if (prev != ctx->device) hipSetDevice(prev);
+    if (e != 0) return hip_fail((hipError_t)e, "knnf_filter launch");
+    return KNNF_OK;
+}
+
+knnf_status knnf_filter_batch(knnf_ctx* ctx, const knnf_frame* frames, int n,
+                              const knnf_plan* plan, void* stream) {
+    if (!ctx) return fail(KNNF_EINVAL, "knnf_filter_batch: NULL context");
+    if (n < 0 || (n > 0 && !frames)) return fail(KNNF_EINVAL, "knnf_filter_batch: bad frame list");
+    if (n == 0) return KNNF_OK;
+    for (int i = 0; i < n; ++i) {
+        knnf_status st = validate(&frames[i], i);
+        if (st != KNNF_OK) return st;
+    }
+    const knnf_plan p = resolve(ctx, plan);
+    if (!plan_ok(p)) return fail(KNNF_EINVAL, "knnf_filter_batch: invalid plan");
+    const int Q = p.queries;
+
+    // Largest strip cost first: long tasks start early, short ones fill the tail.
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return task_cost(frames[a], Q) > task_cost(frames[b], Q);
+    });
+    uint64_t total = 0;
+    std::vector<uint32_t> start(n + 1);
+    for (int k = 0; k < n; ++k) {
+        const knnf_frame& f = frames[order[k]];
+        start[k] = (uint32_t)total;
+        total += (uint64_t)((f.H + Q - 1) / Q) * (uint64_t)f.W;
+        if (total > 0xfff00000ull) return fail(KNNF_EINVAL, "knnf_filter_batch: too much work");
+    }
+    start[n] = (uint32_t)total;
+
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    int prev = 0;
+    hipGetDevice(&prev);
+    if (prev != ctx->device) hipSetDevice(ctx->device);
+    struct Restore {
+        int prev, dev;
+        ~Restore() { if (prev != dev) hipSetDevice(prev); }
+    } restore{prev, ctx->device};
+
+    BatchSlot& s = ctx->slots[ctx->next_slot];
+    ctx->next_slot = (ctx->next_slot + 1) % kSlots;
+    hipError_t e;
+    if (s.recorded) {
+        e = hipEventSynchronize(s.done);
+        if (e != hipSuccess) return hip_fail(e, "batch slot wait");
+        s.recorded = false;
+    }
+    if (s.cap < (size_t)n) {
+        size_t cap = std::max<size_t>(64, s.cap);
+        while (cap < (size_t)n) cap *= 2;
+        if (s.dev) hipFree(s.dev);
+        if (s.host) hipHostFree(s.host);
+        s.dev = s.host = nullptr;
+        s.cap = 0;
+        e = hipMalloc(&s.dev, slot_bytes(cap));
+        if (e != hipSuccess) return fail(KNNF_ENOMEM, "batch table: %s", hipGetErrorString(e));
+        e = hipHostMalloc(&s.host, slot_bytes(cap), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            hipFree(s.dev);
+            s.dev = nullptr;
+            return fail(KNNF_ENOMEM, "batch staging: %s", hipGetErrorString(e));
+        }
+        s.cap = cap;
+    }
+    size_t off_ts = (s.cap * sizeof(knnf::FrameDesc) + 255) & ~size_t(255);
+    size_t off_ctr = off_ts + (((s.cap + 1) * sizeof(uint32_t) + 255) & ~size_t(255));
+    knnf::FrameDesc* hf = (knnf::FrameDesc*)s.host;
+    uint32_t* hts = (uint32_t*)((char*)s.host + off_ts);
+    for (int k = 0; k < n; ++k) hf[k] = to_desc(frames[order[k]]);
+    memcpy(hts, start.data(), (n + 1) * sizeof(uint32_t));
+    hipStream_t hs = (hipStream_t)stream;
+    e = hipMemcpyAsync(s.dev, s.host, n * sizeof(knnf::FrameDesc), hipMemcpyHostToDevice, hs);
+    if (e != hipSuccess) return hip_fail(e, "batch table copy");
+    e = hipMemcpyAsync((char*)s.dev + off_ts, hts, (n + 1) * sizeof(uint32_t),
+                       hipMemcpyHostToDevice, hs);
+    if (e != hipSuccess) return hip_fail(e, "batch prefix copy");
+    uint32_t* d_ctr = (uint32_t*)((char*)s.dev + off_ctr);
+    int rc = knnf::launch_zero_counter(d_ctr, stream);
+    if (rc != 0) return hip_fail((hipError_t)rc, "counter reset");
+    const knnf::LaunchCfg cfg = to_cfg(p);
+    const uint64_t wave_tasks = total;
+    const uint64_t need_blocks = (wave_tasks + p.waves - 1) / p.waves;
+    const int per_cu = knnf::persistent_blocks_per_cu(cfg);
+    const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(need_blocks,
+                                                  (uint64_t)ctx->num_cu * per_cu));
+    rc = knnf::launch_filter_batch((const knnf::FrameDesc*)s.dev,
+                                   (const uint32_t*)((char*)s.dev + off_ts), (uint32_t)n,
+                                   (uint32_t)total, d_ctr, cfg, (int)grid, stream);
+    if (rc != 0) return hip_fail((hipError_t)rc, "knnf_filter_batch launch");
+    e = hipEventRecord(s.done, hs);
+    if (e != hipSuccess) return hip_fail(e, "batch slot record");
+    s.recorded = true;
+    return KNNF_OK;
+}
+
+knnf_status knnf_tune(knnf_ctx* ctx, const knnf_frame* frames, int n, int reps, void* stream,
+                      knnf_plan* best) {
+    if (!ctx) return fail(KNNF_EINVAL, "knnf_tune: NULL context");
+    if (n < 1 || !frames || reps < 1) return fail(KNNF_EINVAL, "knnf_tune: bad arguments");
+    for (int i = 0; i < n; ++i) {
+        knnf_status st = validate(&frames[i], i);
+        if (st != KNNF_OK) return st;
+    }
+    static const int qs[] = {4, 8, 16};
+    static const int ws[] = {1, 2, 4};
+    static const int ss[] = {KNNF_SEARCH_EXHAUSTIVE, KNNF_SEARCH_PRUNED};
+    hipStream_t hs = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(KNNF_EDEVICE, "knnf_tune: event create");
+    float best_ms = 1e30f;
+    knnf_plan bp = ctx->plan;
+    knnf_status result = KNNF_OK;
+    for (int s : ss)
+        for (int q : qs)
+            for (int w : ws) {
+                knnf_plan p{};
+                p.search = s;
+                p.queries = q;
+                p.waves = w;
+                if (!plan_ok(p)) continue;
+                auto run = [&]() -> knnf_status {
+                    return n == 1 ? knnf_filter(ctx, frames, &p, stream)
+                                  : knnf_filter_batch(ctx, frames, n, &p, stream);
+                };
+                knnf_status st = run();  // warm-up
+                if (st != KNNF_OK) { result = st; goto done; }
+                hipEventRecord(e0, hs);
+                for (int r = 0; r < reps && st == KNNF_OK; ++r) st = run();
+                hipEventRecord(e1, hs);
+                if (st != KNNF_OK) { result = st; goto done; }
+                if (hipEventSynchronize(e1) != hipSuccess) {
+                    result = fail(KNNF_EDEVICE, "knnf_tune: synchronize");
+                    goto done;
+                }
+                float ms = 0.f;
+                hipEventElapsedTime(&ms, e0, e1);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    bp = p;
+                }
+            }
+done:
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (result != KNNF_OK) return result;
+    if (best) *best = bp;
+    return KNNF_OK;
+}
+
+}  // extern "C"

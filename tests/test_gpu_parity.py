@@ -1,0 +1,219 @@
+"""GPU parity: the HIP path against the CPU oracle, through the C-ABI.
+
+Bar: neighbour indices, neighbour distances and the class map bit-exact; the
+filtered probabilities within 1e-6 absolute (bit-exact is expected and is
+reported).  Small frames are compared at every pixel; the full-size brain-like
+frame (W 480 x H 380, K = 40, +-14 rows) at sampled pixels plus properties that
+hold at every pixel.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_10631_amd import _lib, inputs
+from paper_2404_10631_amd.frames import DeviceFrame, current_stream
+
+pytestmark = pytest.mark.gpu
+
+PROB_TOL = 1e-6
+
+EXH8 = dict(search=0, queries=8, waves=2)
+PRU8 = dict(search=1, queries=8, waves=2)
+ALL_PLANS = [dict(search=s, queries=q, waves=w)
+             for s in (0, 1) for q in (4, 8, 16) for w in (1, 2, 4) if not (q == 16 and w == 4)]
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    assert torch.cuda.is_available(), "no GPU visible"
+    c = _lib.knnf_create(0)
+    yield c
+    _lib.knnf_destroy(c)
+
+
+def run_gpu(ctx, pc1, prob, K, R, lam, plan, with_nbr=True):
+    import torch
+
+    df = DeviceFrame(pc1, prob, K, R, lam, with_nbr=with_nbr)
+    df.clear_outputs()
+    _lib.knnf_filter(ctx, df.as_c(), plan, current_stream())
+    torch.cuda.synchronize()
+    return df.results()
+
+
+def assert_parity(gpu, ref, label=""):
+    go, gc, gn, gd = gpu
+    ro, rc, rn, rd = ref
+    if rn is not None:
+        bad = np.argwhere(np.any(gn != rn, axis=-1))
+        assert bad.size == 0, f"{label}: nbr differs at {bad[:5].tolist()} (of {len(bad)})"
+        assert np.array_equal(gd.view(np.uint32), rd.view(np.uint32)), f"{label}: dist differs"
+    assert np.array_equal(gc, rc), f"{label}: class differs at {np.argwhere(gc != rc)[:5].tolist()}"
+    err = float(np.max(np.abs(go.astype(np.float64) - ro.astype(np.float64)))) if go.size else 0.0
+    assert err <= PROB_TOL, f"{label}: prob max abs err {err}"
+    return err
+
+
+CASES = [
+    # label, generator, H, W, K, R, lam
+    ("one-pixel", "unif", 1, 1, 1, 0, 0.01),
+    ("one-row-wide", "unif", 1, 70, 5, 0, 0.01),
+    ("K-whole-frame", "unif", 3, 5, 15, 2, 0.01),
+    ("K64-R0", "unif", 5, 200, 64, 0, 0.01),
+    ("R-beyond-H", "brain", 17, 130, 40, 14, 0.01),
+    ("one-column", "unif", 100, 1, 6, 5, 0.01),
+    ("ragged-brain", "brain", 33, 129, 16, 7, 0.01),
+    ("derma-50", "derma", 50, 50, 16, 7, 0.01),
+    ("lambda-one", "unif", 25, 90, 12, 4, 1.0),
+    ("tall-narrow", "brain", 150, 37, 40, 14, 0.01),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: c[0])
+@pytest.mark.parametrize("plan", [EXH8, PRU8, dict(search=1, queries=4, waves=4),
+                                  dict(search=0, queries=16, waves=1)],
+                         ids=lambda p: f"s{p['search']}q{p['queries']}w{p['waves']}")
+def test_small_frames_bit_exact(ctx, case, plan):
+    label, gen, H, W, K, R, lam = case
+    pc1, prob = inputs.GENERATORS[gen](H, W, 31)
+    say(f"case {label} H={H} W={W} K={K} R={R} lam={lam} plan={plan}")
+    ref = oracle.knn_filter(pc1, prob, K, R, lam)
+    assert_parity(run_gpu(ctx, pc1, prob, K, R, lam, plan), ref, label)
+
+
+@pytest.mark.parametrize("plan", ALL_PLANS, ids=lambda p: f"s{p['search']}q{p['queries']}w{p['waves']}")
+def test_config0_all_plans(ctx, plan):
+    """One 64 x 64 uniform frame, K = 8, +-4 rows, lambda = 0.01, seed 0."""
+    spec = inputs.config0().frames[0]
+    pc1, prob = spec.make()
+    say(f"config0 plan={plan}")
+    ref = oracle.knn_filter(pc1, prob, spec.K, spec.R, spec.lam)
+    assert_parity(run_gpu(ctx, pc1, prob, spec.K, spec.R, spec.lam, plan), ref, "config0")
+
+
+def test_ties_constant_band_lambda_zero(ctx):
+    """Every distance equal: the order is decided by the linear index alone."""
+    H, W, K, R = 20, 70, 10, 3
+    pc1 = np.full((H, W), 0.5, np.float32)
+    _, prob = inputs.g_unif(H, W, 4)
+    ref = oracle.knn_filter(pc1, prob, K, R, 0.0)
+    for plan in (EXH8, PRU8):
+        say(f"constant band lambda 0 plan={plan}")
+        assert_parity(run_gpu(ctx, pc1, prob, K, R, 0.0, plan), ref, "const-l0")
+
+
+def test_ties_dyadic(ctx):
+    rng = np.random.default_rng(9)
+    H, W, K, R = 31, 45, 24, 5
+    pc1 = (rng.integers(0, 5, size=(H, W)) / 4.0).astype(np.float32)
+    _, prob = inputs.g_unif(H, W, 5)
+    ref = oracle.knn_filter(pc1, prob, K, R, 0.25)
+    for plan in (EXH8, PRU8):
+        say(f"dyadic ties plan={plan}")
+        assert_parity(run_gpu(ctx, pc1, prob, K, R, 0.25, plan), ref, "dyadic")
+
+
+@pytest.mark.parametrize("C", [1, 3, 16])
+def test_class_counts(ctx, C):
+    H, W, K, R = 19, 77, 12, 3
+    pc1, prob = inputs.g_brain(H, W, 8, C=C)
+    say(f"classes C={C}")
+    ref = oracle.knn_filter(pc1, prob, K, R, 0.01)
+    assert_parity(run_gpu(ctx, pc1, prob, K, R, 0.01, PRU8), ref, f"C{C}")
+
+
+def test_without_neighbour_outputs(ctx):
+    pc1, prob = inputs.g_brain(40, 90, 2)
+    ref = oracle.knn_filter(pc1, prob, 20, 6, 0.01, with_nbr=False)
+    say("no nbr outputs")
+    assert_parity(run_gpu(ctx, pc1, prob, 20, 6, 0.01, EXH8, with_nbr=False), ref, "no-nbr")
+
+
+@pytest.mark.parametrize("plan", [EXH8, PRU8], ids=["exhaustive", "pruned"])
+def test_config1_full_size_sampled(ctx, plan):
+    """Brain-like frame W 480 x H 380, K = 40, +-14 rows: sampled pixels
+    against the oracle; properties at every pixel."""
+    spec = inputs.config1().frames[0]
+    pc1, prob = spec.make()
+    say(f"config1 full size plan={plan}")
+    go, gc, gn, gd = run_gpu(ctx, pc1, prob, spec.K, spec.R, spec.lam, plan)
+    H, W, K = spec.H, spec.W, spec.K
+    rng = np.random.default_rng(123)
+    edge = np.concatenate([np.arange(W), (H - 1) * W + np.arange(W),
+                           np.arange(H) * W, np.arange(H) * W + W - 1])
+    pix = np.unique(np.concatenate([rng.integers(0, H * W, 2500), edge[::7]]))
+    ro, rc, rn, rd = oracle.knn_pixels(pc1, prob, K, spec.R, spec.lam, pix)
+    flat = lambda a: a.reshape(H * W, -1)[pix]
+    assert_parity((flat(go), flat(gc).reshape(-1), flat(gn), flat(gd)), (ro, rc, rn, rd), "config1")
+    # every pixel: itself first at distance 0, ascending distances, rows sum to 1
+    lin = np.arange(H * W).reshape(H, W)
+    assert np.array_equal(gn[..., 0], lin)
+    assert np.all(gd[..., 0] == 0)
+    assert np.all(np.diff(gd, axis=-1) >= 0)
+    assert np.all((gn >= 0) & (gn < H * W))
+    assert np.max(np.abs(go.astype(np.float64).sum(-1) - 1.0)) <= 1e-5
+    rows = gn // W
+    assert np.all(np.abs(rows - lin[..., None] // W) <= spec.R)
+
+
+def test_exhaustive_equals_pruned_and_deterministic(ctx):
+    spec = inputs.config1().frames[0]
+    pc1, prob = spec.make()
+    say("config1 exhaustive vs pruned vs repeat")
+    a = run_gpu(ctx, pc1, prob, spec.K, spec.R, spec.lam, EXH8)
+    b = run_gpu(ctx, pc1, prob, spec.K, spec.R, spec.lam, PRU8)
+    c = run_gpu(ctx, pc1, prob, spec.K, spec.R, spec.lam, PRU8)
+    for x, y, z in zip(a, b, c):
+        assert np.array_equal(x, y) and np.array_equal(y, z)
+
+
+def test_batch_matches_single_frames_and_oracle(ctx):
+    import torch
+
+    specs = [inputs.FrameSpec("brain", 70, 130, 1, K=40, R=14),
+             inputs.FrameSpec("derma", 50, 50, 2, K=16, R=7),
+             inputs.FrameSpec("unif", 9, 300, 3, K=8, R=4),
+             inputs.FrameSpec("derma", 50, 50, 4, K=16, R=7),
+             inputs.FrameSpec("brain", 130, 61, 5, K=40, R=14),
+             inputs.FrameSpec("unif", 1, 1, 6, K=1, R=0),
+             inputs.FrameSpec("brain", 64, 64, 7, K=24, R=3, lam=0.05)]
+    for plan in (EXH8, PRU8, dict(search=1, queries=16, waves=1)):
+        say(f"batch of {len(specs)} plan={plan}")
+        data = [s.make() for s in specs]
+        batch = [DeviceFrame(p, q, s.K, s.R, s.lam) for s, (p, q) in zip(specs, data)]
+        for df in batch:
+            df.clear_outputs()
+        _lib.knnf_filter_batch(ctx, [df.as_c() for df in batch], plan, current_stream())
+        torch.cuda.synchronize()
+        for s, (p, q), df in zip(specs, data, batch):
+            got = df.results()
+            single = run_gpu(ctx, p, q, s.K, s.R, s.lam, plan)
+            for x, y in zip(got, single):
+                assert np.array_equal(x, y)
+            assert_parity(got, oracle.knn_filter(p, q, s.K, s.R, s.lam), f"batch {s}")
+
+
+def test_invalid_frame_is_rejected_before_launch(ctx):
+    pc1, prob = inputs.g_unif(4, 4, 0)
+    df = DeviceFrame(pc1, prob, 9, 0, 0.01)  # K = 9 > window of 4
+    with pytest.raises(_lib.KnnfError) as ei:
+        _lib.knnf_filter(ctx, df.as_c(), None, current_stream())
+    assert ei.value.status == _lib.KNNF_EINVAL
+    with pytest.raises(_lib.KnnfError):
+        _lib.knnf_filter_batch(ctx, [df.as_c()], None, current_stream())
+
+
+def test_single_hip_runtime_loaded(ctx):
+    maps = open("/proc/self/maps").read()
+    libs = {line.split()[-1] for line in maps.splitlines() if "libamdhip64" in line}
+    assert len(libs) == 1, libs
+    assert any("libknnf.so" in line for line in maps.splitlines())
