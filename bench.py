@@ -39,7 +39,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--plan", default="exhaustive", choices=["exhaustive", "pruned"])
-    ap.add_argument("--queries", type=int, default=8)
+    ap.add_argument("--tile-rows", type=int, default=2)
+    ap.add_argument("--tile-cols", type=int, default=8)
     ap.add_argument("--waves", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample")
@@ -86,8 +87,8 @@ def main():
     frame = DeviceFrame(pc1, prob, spec.K, spec.R, spec.lam, with_nbr=False)
     cf = frame.as_c()
     ctx = _lib.knnf_create(0)
-    plan = {"search": 0 if args.plan == "exhaustive" else 1, "queries": args.queries,
-            "waves": args.waves}
+    plan = {"search": 0 if args.plan == "exhaustive" else 1, "tile_rows": args.tile_rows,
+            "tile_cols": args.tile_cols, "waves": args.waves}
     stream = current_stream()
 
     for _ in range(args.warmup):

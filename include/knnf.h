@@ -111,15 +111,16 @@ typedef enum { KNNF_SEARCH_EXHAUSTIVE = 0, KNNF_SEARCH_PRUNED = 1 } knnf_search;
 /*
  * Launch plan: how a frame is cut into work.
  *   search        one of knnf_search
- *   queries       pixels per wavefront task (a vertical strip); 4, 8 or 16
+ *   tile_rows     query pixels per wavefront task = tile_rows x tile_cols;
+ *   tile_cols     supported tiles (rows x cols): 1x8, 1x16, 2x4, 2x8, 4x4
  *   waves         wavefronts per workgroup; 1, 2 or 4
- * A zero field means "library default / tuned value".
+ * A zero field means "the context's default".  search = 0 is exhaustive.
  */
 typedef struct {
     int32_t search;
-    int32_t queries;
+    int32_t tile_rows;
+    int32_t tile_cols;
     int32_t waves;
-    int32_t reserved;
 } knnf_plan;
 
 /* Create a context on HIP device `device` (ordinal).  *out is NULL on error. */

@@ -45,11 +45,12 @@ class knnf_frame(ctypes.Structure):
 
 
 class knnf_plan(ctypes.Structure):
-    _fields_ = [("search", ctypes.c_int32), ("queries", ctypes.c_int32),
-                ("waves", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+    _fields_ = [("search", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
+                ("tile_cols", ctypes.c_int32), ("waves", ctypes.c_int32)]
 
     def as_dict(self):
-        return {"search": self.search, "queries": self.queries, "waves": self.waves}
+        return {"search": self.search, "tile_rows": self.tile_rows,
+                "tile_cols": self.tile_cols, "waves": self.waves}
 
 
 class KnnfError(RuntimeError):
@@ -114,8 +115,8 @@ def _plan_ptr(plan):
     if plan is None:
         return None
     if isinstance(plan, dict):
-        p = knnf_plan(int(plan.get("search", 0)), int(plan.get("queries", 0)),
-                      int(plan.get("waves", 0)), 0)
+        p = knnf_plan(int(plan.get("search", 0)), int(plan.get("tile_rows", 0)),
+                      int(plan.get("tile_cols", 0)), int(plan.get("waves", 0)))
     else:
         p = plan
     return ctypes.byref(p)

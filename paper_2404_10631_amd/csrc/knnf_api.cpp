@@ -69,8 +69,6 @@ struct knnf_ctx {
     std::mutex mu;
     BatchSlot slots[kSlots];
     int next_slot = 0;
-    // tuned plans: bucket key -> plan
-    std::map<uint64_t, knnf_plan> tuned;
 };
 
 namespace {
@@ -78,24 +76,29 @@ namespace {
 knnf_plan default_plan() {
     knnf_plan p{};
     p.search = KNNF_SEARCH_EXHAUSTIVE;
-    p.queries = 8;
+    p.tile_rows = 2;
+    p.tile_cols = 8;
     p.waves = 2;
     return p;
 }
 
+const int kShapes[][2] = {{1, 8}, {1, 16}, {2, 4}, {2, 8}, {4, 4}};
+
 bool plan_ok(const knnf_plan& p) {
     if (p.search != KNNF_SEARCH_EXHAUSTIVE && p.search != KNNF_SEARCH_PRUNED) return false;
-    if (p.queries != 4 && p.queries != 8 && p.queries != 16) return false;
+    bool shape = false;
+    for (const auto& s : kShapes) shape |= (p.tile_rows == s[0] && p.tile_cols == s[1]);
+    if (!shape) return false;
     if (p.waves != 1 && p.waves != 2 && p.waves != 4) return false;
-    if (p.queries == 16 && p.waves == 4) return false;
     return true;
 }
 
 knnf_plan resolve(const knnf_ctx* ctx, const knnf_plan* p) {
     knnf_plan r = ctx->plan;
     if (p) {
-        if (p->search) r.search = p->search;
-        if (p->queries) r.queries = p->queries;
+        r.search = p->search;
+        if (p->tile_rows) r.tile_rows = p->tile_rows;
+        if (p->tile_cols) r.tile_cols = p->tile_cols;
         if (p->waves) r.waves = p->waves;
     }
     return r;
@@ -103,7 +106,8 @@ knnf_plan resolve(const knnf_ctx* ctx, const knnf_plan* p) {
 
 knnf::LaunchCfg to_cfg(const knnf_plan& p) {
     knnf::LaunchCfg c;
-    c.queries = p.queries;
+    c.rows = p.tile_rows;
+    c.cols = p.tile_cols;
     c.waves = p.waves;
     c.pruned = p.search == KNNF_SEARCH_PRUNED ? 1 : 0;
     return c;
@@ -150,7 +154,7 @@ knnf_status validate(const knnf_frame* f, int index) {
     return KNNF_OK;
 }
 
-// Relative cost of one strip task of a frame (candidate pairs per strip).
+// Relative cost of one tile task of a frame (candidate pairs per tile).
 double task_cost(const knnf_frame& f, int Q) {
     const double rows = std::min<double>(2.0 * f.R + 1.0, f.H);
     return (double)Q * rows * (double)f.W;
@@ -264,7 +268,8 @@ knnf_status knnf_filter_batch(knnf_ctx* ctx, const knnf_frame* frames, int n,
     }
     const knnf_plan p = resolve(ctx, plan);
     if (!plan_ok(p)) return fail(KNNF_EINVAL, "knnf_filter_batch: invalid plan");
-    const int Q = p.queries;
+    const int QR = p.tile_rows, QC = p.tile_cols;
+    const int Q = QR * QC;
 
     // Largest strip cost first: long tasks start early, short ones fill the tail.
     std::vector<int> order(n);
@@ -277,7 +282,7 @@ knnf_status knnf_filter_batch(knnf_ctx* ctx, const knnf_frame* frames, int n,
     for (int k = 0; k < n; ++k) {
         const knnf_frame& f = frames[order[k]];
         start[k] = (uint32_t)total;
-        total += (uint64_t)((f.H + Q - 1) / Q) * (uint64_t)f.W;
+        total += (uint64_t)((f.H + QR - 1) / QR) * (uint64_t)((f.W + QC - 1) / QC);
         if (total > 0xfff00000ull) return fail(KNNF_EINVAL, "knnf_filter_batch: too much work");
     }
     start[n] = (uint32_t)total;
@@ -355,7 +360,6 @@ knnf_status knnf_tune(knnf_ctx* ctx, const knnf_frame* frames, int n, int reps, 
         knnf_status st = validate(&frames[i], i);
         if (st != KNNF_OK) return st;
     }
-    static const int qs[] = {4, 8, 16};
     static const int ws[] = {1, 2, 4};
     static const int ss[] = {KNNF_SEARCH_EXHAUSTIVE, KNNF_SEARCH_PRUNED};
     hipStream_t hs = (hipStream_t)stream;
@@ -366,11 +370,12 @@ knnf_status knnf_tune(knnf_ctx* ctx, const knnf_frame* frames, int n, int reps, 
     knnf_plan bp = ctx->plan;
     knnf_status result = KNNF_OK;
     for (int s : ss)
-        for (int q : qs)
+        for (const auto& sh : kShapes)
             for (int w : ws) {
                 knnf_plan p{};
                 p.search = s;
-                p.queries = q;
+                p.tile_rows = sh[0];
+                p.tile_cols = sh[1];
                 p.waves = w;
                 if (!plan_ok(p)) continue;
                 auto run = [&]() -> knnf_status {

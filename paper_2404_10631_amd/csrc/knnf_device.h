@@ -20,7 +20,7 @@ struct FrameDesc {
 };
 
 // Work accounting for the persistent batched launch: frame f owns the task
-// ids [task_start[f], task_start[f+1]); a task is one wavefront strip.
+// ids [task_start[f], task_start[f+1]); a task is one wavefront tile.
 struct BatchHeader {
     uint32_t nframes;
     uint32_t total_tasks;
@@ -28,7 +28,8 @@ struct BatchHeader {
 
 // Kernel launch configuration chosen by the host (see knnf_plan).
 struct LaunchCfg {
-    int queries;   // pixels per wavefront strip: 4, 8, 16
+    int rows;      // tile rows (query pixels per wavefront = rows * cols)
+    int cols;      // tile columns
     int waves;     // wavefronts per workgroup: 1, 2, 4
     int pruned;    // 0 exhaustive, 1 pruned
 };

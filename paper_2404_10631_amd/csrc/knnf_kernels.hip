@@ -81,269 +81,502 @@ __device__ __forceinline__ uint32_t shfl(uint32_t v, int src) {
 __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
     return ((uint64_t)shfl((uint32_t)(v >> 32), src) << 32) | (uint64_t)shfl((uint32_t)v, src);
 }
+__device__ __forceinline__ uint32_t xlane_read(uint32_t v, int lane) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
+}
 __device__ __forceinline__ uint64_t make_key(float d, int idx) {
     return ((uint64_t)__float_as_uint(d) << 32) | (uint64_t)(uint32_t)idx;
 }
 
+// ---- cross-lane exchange with the partner lane L ^ J (no LDS traffic
+// except J = 4, which uses the LDS crossbar swizzle)
+template <int J>
+__device__ __forceinline__ uint32_t xlane(uint32_t v) {
+    if constexpr (J == 1) {
+        return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xF, 0xF, false);
+    } else if constexpr (J == 2) {
+        return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xF, 0xF, false);
+    } else if constexpr (J == 4) {
+        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (4 << 10));
+    } else if constexpr (J == 8) {
+        return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x128, 0xF, 0xF, false);
+    } else if constexpr (J == 16) {
+        // permlane16_swap(v, v) yields rows {0,0,2,2} and {1,1,3,3}
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (lane_id() & 16) ? r[0] : r[1];
+    } else {
+        // permlane32_swap(v, v) yields halves {lo,lo} and {hi,hi}
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (lane_id() & 32) ? r[0] : r[1];
+    }
+}
+
+// Compare-exchange of 64-bit keys (hi, lo) with partner L ^ J inside bitonic
+// stage S (S = 64: the final, all-ascending stage).
+template <int S, int J>
+__device__ __forceinline__ void cx_key(uint32_t& hi, uint32_t& lo) {
+    const int L = lane_id();
+    const uint32_t ph = xlane<J>(hi), pl = xlane<J>(lo);
+    const uint64_t me = ((uint64_t)hi << 32) | lo, ot = ((uint64_t)ph << 32) | pl;
+    const bool flip = ((L & J) != 0) != (S < WAVE && (L & S) != 0);
+    const bool take = (ot < me) != flip;  // keys are unique apart from KEY_INF
+    hi = take ? ph : hi;
+    lo = take ? pl : lo;
+}
+
+template <int S, int J>
+__device__ __forceinline__ void stage_key(uint32_t& hi, uint32_t& lo) {
+    cx_key<S, J>(hi, lo);
+    if constexpr (J > 1) stage_key<S, J / 2>(hi, lo);
+}
+
 // Ascending bitonic sort of one 64-bit key per lane across the wavefront.
 __device__ __forceinline__ uint64_t sort64(uint64_t key) {
-    const int L = lane_id();
-#pragma unroll
-    for (int k = 2; k <= WAVE; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            const uint64_t other = shfl64(key, L ^ j);
-            const bool up = (k == WAVE) || ((L & k) == 0);
-            const bool lower = (L & j) == 0;
-            const bool take = (lower == up) ? (other < key) : (key < other);
-            key = take ? other : key;
-        }
-    }
-    return key;
+    uint32_t hi = (uint32_t)(key >> 32), lo = (uint32_t)key;
+    stage_key<2, 1>(hi, lo);
+    stage_key<4, 2>(hi, lo);
+    stage_key<8, 4>(hi, lo);
+    stage_key<16, 8>(hi, lo);
+    stage_key<32, 16>(hi, lo);
+    stage_key<64, 32>(hi, lo);
+    return ((uint64_t)hi << 32) | lo;
 }
 
 // a, b ascending across lanes; returns the 64 smallest of both, ascending.
 __device__ __forceinline__ uint64_t merge64(uint64_t a, uint64_t b) {
     const int L = lane_id();
     const uint64_t rb = shfl64(b, WAVE - 1 - L);
-    uint64_t key = rb < a ? rb : a;  // bitonic: the 64 smallest of a and b
-#pragma unroll
-    for (int j = WAVE / 2; j > 0; j >>= 1) {
-        const uint64_t other = shfl64(key, L ^ j);
-        const bool lower = (L & j) == 0;
-        const bool take = lower ? (other < key) : (key < other);
-        key = take ? other : key;
-    }
-    return key;
+    const uint64_t key = rb < a ? rb : a;  // bitonic: the 64 smallest of a and b
+    uint32_t hi = (uint32_t)(key >> 32), lo = (uint32_t)key;
+    stage_key<64, 32>(hi, lo);
+    return ((uint64_t)hi << 32) | lo;
 }
 
-template <int Q>
-struct alignas(16) WaveState {
-    uint64_t list[Q][WAVE];   // sorted top-K per query (lanes >= K hold KEY_INF)
-    uint64_t pend[Q][WAVE];   // candidates that passed the tau test, unsorted
-    float a2t[A2ROWS][Q];     // fl32(a*a) for a block of window rows
-    uint64_t tau[Q];          // current upper bound on the K-th key
-    float iq[Q];              // I of each query pixel
+// Compare-exchange of 32-bit values (min/max) for the pass-A bound.
+template <int S, int J>
+__device__ __forceinline__ void cx_u32(uint32_t& v) {
+    const int L = lane_id();
+    const uint32_t p = xlane<J>(v);
+    const bool keep_min = ((L & J) != 0) == (S < WAVE && (L & S) != 0);
+    v = keep_min ? min(v, p) : max(v, p);
+}
+
+template <int S, int J>
+__device__ __forceinline__ void stage_u32(uint32_t& v) {
+    cx_u32<S, J>(v);
+    if constexpr (J > 1) stage_u32<S, J / 2>(v);
+}
+
+__device__ __forceinline__ uint32_t sort64_u32(uint32_t v) {
+    stage_u32<2, 1>(v);
+    stage_u32<4, 2>(v);
+    stage_u32<8, 4>(v);
+    stage_u32<16, 8>(v);
+    stage_u32<32, 16>(v);
+    stage_u32<64, 32>(v);
+    return v;
+}
+
+// Per-wavefront LDS state of one tile of QR x QC query pixels.
+template <int QR, int QC>
+struct alignas(16) TileState {
+    static constexpr int Q = QR * QC;
+    uint64_t pend[Q][WAVE];   // keys of candidates that passed the bound, unsorted
+    uint32_t list[Q][WAVE];   // sorted top-K linear indices (first listn valid);
+                              // before the scan: pass-A block distances
     float sums[Q][MAXC];      // class sums for the argmax
-    int cnt[Q];               // pending entries
+    uint64_t tau[Q];          // current bound on the K-th key of each query
+    uint32_t tauhi[Q];        // its distance bits (high word)
+    float a2t[A2ROWS][QR];    // fl32(a*a) for a block of window rows (+inf: inactive)
+    float iq[Q];              // I of each query pixel (NaN for pixels off the frame)
     int listn[Q];             // valid list entries (<= K)
+    int cnt[Q];               // pending entries (mirror of the scan's registers)
+    int ovu[Q];               // first row of the group not yet appended (overflow)
 };
 
-// Row coordinate feature fr(x) = fl32(lambda * (float)x).
+// Coordinate feature fr(x) = fl32(lambda * (float)x).
 __device__ __forceinline__ float feat(float lam, int x) { return lam * (float)x; }
 
-// Merge query q's pending buffer into its top-K list and tighten tau.
-template <int Q>
-__device__ void flush_query(WaveState<Q>& S, int q, int K) {
-    const int L = lane_id();
-    wave_sync();
-    const int cnt = uni(S.cnt[q]);
-    const int listn = uni(S.listn[q]);
-    uint64_t p = (L < cnt) ? S.pend[q][L] : KEY_INF;
-    p = sort64(p);
-    uint64_t l = p;
-    if (listn > 0) l = merge64(S.list[q][L], p);
-    if (L >= K) l = KEY_INF;
-    S.list[q][L] = l;
-    const int nl = min(K, listn + cnt);
-    const uint64_t kth = uni64(shfl64(l, K - 1));
-    const uint64_t tau = uni64(S.tau[q]);
-    wave_sync();
-    if (L == 0) {
-        S.listn[q] = nl;
-        S.cnt[q] = 0;
-        if (nl == K && kth < tau) S.tau[q] = kth;
-    }
-    wave_sync();
+// Eq. 1 between query (r, c, iq) and the candidate with linear index idx,
+// evaluated exactly as in the scan loop.
+__device__ __forceinline__ float dist_to(const float* __restrict__ pc1, int W, float lam, int r,
+                                         int c, float iq, uint32_t idx) {
+    const int i = (int)(idx / (uint32_t)W);
+    const int j = (int)idx - i * W;
+    const float a = feat(lam, r) - feat(lam, i);
+    const float a2 = a * a;
+    const float b = feat(lam, c) - feat(lam, j);
+    const float e = iq - pc1[idx];
+    return fmaf(e, e, fmaf(b, b, a2));
 }
 
-// Append the lanes with key <= tau of query q to its pending buffer.
-template <int Q>
-__device__ void push_survivors(WaveState<Q>& S, int q, int K, bool valid, uint64_t key) {
+// Merge query q's pending candidates into its sorted top-K list.  Returns the
+// new K-th key (KEY_INF while fewer than K candidates are known).  With
+// `final`, also writes the neighbour outputs of the query pixel.
+template <int QR, int QC>
+__device__ __forceinline__ uint64_t flush_query(TileState<QR, QC>& S, const FrameDesc& f, int r0,
+                                             int c0, int q, int cnt, bool final) {
     const int L = lane_id();
-    uint64_t tau = uni64(S.tau[q]);
-    bool ok = valid && key <= tau;
-    uint64_t m = ballot(ok);
-    if (m == 0) return;
-    int cnt = uni(S.cnt[q]);
-    int n = __builtin_popcountll(m);
-    if (cnt + n > WAVE) {
-        flush_query(S, q, K);
-        tau = uni64(S.tau[q]);
-        ok = valid && key <= tau;
-        m = ballot(ok);
-        n = __builtin_popcountll(m);
-        cnt = 0;
-    }
-    if (ok) S.pend[q][cnt + mbcnt(m)] = key;
-    wave_sync();
-    if (L == 0) S.cnt[q] = cnt + n;
-    wave_sync();
-}
-
-// Pass A for query q: tau = K-th key of a compact block of window candidates.
-template <int Q>
-__device__ void seed_query(WaveState<Q>& S, const FrameDesc& f, int q, int r, int c) {
-    const int L = lane_id();
-    const int H = f.H, W = f.W, R = f.R, K = f.K;
+    const int W = f.W, K = f.K;
     const float lam = f.lambda;
-    const int i0 = max(0, r - R), i1 = min(H - 1, r + R);
+    const int r = r0 + q / QC, c = c0 + q % QC;
+    wave_sync();
+    const float iq = S.iq[q];
+    const int listn = uni(S.listn[q]);
+    uint64_t key = KEY_INF;
+    if (cnt > 0) {
+        if (L < cnt) key = S.pend[q][L];
+        key = sort64(key);
+    }
+    if (listn > 0) {
+        uint64_t lk = KEY_INF;
+        if (L < listn) {
+            const uint32_t idx = S.list[q][L];
+            lk = make_key(dist_to(f.pc1, W, lam, r, c, iq, idx), (int)idx);
+        }
+        key = (cnt > 0) ? merge64(lk, key) : lk;
+    }
+    if (L >= K) key = KEY_INF;
+    const int nl = min(K, listn + cnt);
+    wave_sync();
+    if (L < K) S.list[q][L] = (uint32_t)key;
+    if (final && L < K) {
+        const size_t pix = (size_t)r * W + c;
+        if (f.out_nbr) f.out_nbr[pix * K + L] = (int32_t)(uint32_t)key;
+        if (f.out_dist) f.out_dist[pix * K + L] = __uint_as_float((uint32_t)(key >> 32));
+    }
+    const uint64_t kth = uni64(shfl64(key, K - 1));
+    if (L == 0) S.listn[q] = nl;
+    wave_sync();
+    return nl == K ? kth : KEY_INF;
+}
+
+// Pass A: lane L's candidate in a compact block of query (r, c)'s window: 8 x 8
+// pixels where the window allows (fewer rows, more columns near short
+// windows); returns false for lanes past the frame's right edge.
+__device__ __forceinline__ bool block_cand(const FrameDesc& f, int r, int c, int L, int& i, int& j) {
+    const int i0 = max(0, r - f.R), i1 = min(f.H - 1, r + f.R);
     const int nr = i1 - i0 + 1;
-    int lbr = 0;  // log2 of block rows: 8, 4, 2 or 1 rows
-    while (lbr < 3 && (2 << lbr) <= nr) ++lbr;
+    const int lbr = nr >= 8 ? 3 : (nr >= 4 ? 2 : (nr >= 2 ? 1 : 0));
     const int br = 1 << lbr;
     const int lbc = 6 - lbr;
     const int bc = 1 << lbc;
     const int rb = min(max(r - br / 2, i0), i1 - br + 1);
-    const int cb = max(0, min(c - bc / 2, W - bc));
-    const int i = rb + (L >> lbc);
-    const int j = cb + (L & (bc - 1));
-    const bool valid = j < W;
-    uint64_t key = KEY_INF;
-    if (valid) {
-        const float a = feat(lam, r) - feat(lam, i);
-        const float b = feat(lam, c) - feat(lam, j);
-        const float e = S.iq[q] - f.pc1[(size_t)i * W + j];
-        const float d = fmaf(e, e, fmaf(b, b, a * a));
-        key = make_key(d, i * W + j);
-    }
-    key = sort64(key);
-    const uint64_t kth = uni64(shfl64(key, K - 1));
-    wave_sync();
-    if (L == 0) {
-        S.tau[q] = kth;
-        S.cnt[q] = 0;
-        S.listn[q] = 0;
-    }
-    wave_sync();
+    const int cb = max(0, min(c - bc / 2, f.W - bc));
+    i = rb + (L >> lbc);
+    j = cb + (L & (bc - 1));
+    return j < f.W;
 }
 
-// Process one strip: queries (r0 + q, c) for q < nq.
-template <int Q, bool PRUNE>
-__device__ void process_strip(WaveState<Q>& S, const FrameDesc& f, int c, int r0) {
+// Process one tile: query pixels (r0 + qr, c0 + qc), qr < QR, qc < QC.
+template <int QR, int QC, bool PRUNE>
+__device__ __forceinline__ void process_tile(TileState<QR, QC>& S, const FrameDesc& f, int r0,
+                                             int c0) {
+    constexpr int Q = QR * QC;
     const int L = lane_id();
     const int H = f.H, W = f.W, R = f.R, K = f.K, C = f.C;
     const float lam = f.lambda;
-    const int nq = min(Q, H - r0);
+    const int nqr = min(QR, H - r0), nqc = min(QC, W - c0);
     const float* __restrict__ pc1 = f.pc1;
-
-    // ---- query values (uniform, kept in VGPRs to spare scalar registers)
-    if (L < Q) S.iq[L] = (L < nq) ? pc1[(size_t)(r0 + L) * W + c] : 0.0f;
-    wave_sync();
-    float iq[Q];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) iq[q] = S.iq[q];
-
-    // ---- pass A: initial bounds
-    for (int q = 0; q < nq; ++q) seed_query(S, f, q, r0 + q, c);
-
-    uint32_t tauhi[Q];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) tauhi[q] = q < nq ? (uint32_t)(S.tau[q] >> 32) : 0u;
-
-    // ---- pass B: every window candidate, chunks of 64 columns centred on c
-    const float fcq = feat(lam, c);
-    const int rlo = max(0, r0 - R);
-    const int rhi = min(H - 1, r0 + nq - 1 + R);
-    const int nright = (W + 31 - c) / WAVE;  // chunks m = 1..nright exist to the right
-    const int nleft = (c + 31) / WAVE;       // chunks m = -1..-nleft exist to the left
-    const int nsteps = 2 * max(nleft, nright);
     const float qnan = __int_as_float(0x7fc00000);
     const float pinf = __int_as_float(0x7f800000);
 
-    for (int t = 0; t <= nsteps; ++t) {
-        const int m = (t & 1) ? (t + 1) / 2 : -(t / 2);
-        if (m > nright || -m > nleft) continue;
-        const int jbase = c - 32 + WAVE * m;
-        const int j = jbase + L;
-        const bool valid = (unsigned)j < (unsigned)W;
-        const float b = fcq - feat(lam, j);
-
-        for (int blk = rlo; blk <= rhi; blk += A2ROWS) {
-            const int nb = min(A2ROWS, rhi - blk + 1);
-            // a2 table for rows blk .. blk+A2ROWS-1; +inf marks a row outside
-            // query q's window (or a query beyond the frame), which makes the
-            // inner loop branch-free: d = +inf never passes a finite bound.
-            wave_sync();
-            for (int u = L; u < A2ROWS * Q; u += WAVE) {
-                const int rr = u / Q, q = u % Q;
-                const int r = r0 + q, i = blk + rr;
-                const bool act = q < nq && i >= r - R && i <= r + R;
-                const float a = feat(lam, r) - feat(lam, i);
-                S.a2t[rr][q] = act ? a * a : pinf;
-            }
-            wave_sync();
-
-            float ip_next = valid ? pc1[(size_t)blk * W + j] : qnan;
-            for (int rr = 0; rr < nb; ++rr) {
-                const int i = blk + rr;
-                const float ip = ip_next;
-                if (rr + 1 < nb) ip_next = valid ? pc1[(size_t)(i + 1) * W + j] : qnan;
-                float a2[Q];
-#pragma unroll
-                for (int q = 0; q < Q; ++q) a2[q] = S.a2t[rr][q];
-                uint64_t anyb = 0;
-#pragma unroll
-                for (int q = 0; q < Q; ++q) {
-                    const float e = iq[q] - ip;
-                    const float tt = fmaf(b, b, a2[q]);
-                    const float d = fmaf(e, e, tt);
-                    anyb |= ballot(__float_as_uint(d) <= tauhi[q]);
-                }
-                if (anyb) {
-                    for (int q = 0; q < nq; ++q) {
-                        const float a2q = unif(S.a2t[rr][q]);
-                        if (__float_as_uint(a2q) == 0x7f800000u) continue;  // row outside q's window
-                        const float e = S.iq[q] - ip;
-                        const float d = fmaf(e, e, fmaf(b, b, a2q));
-                        push_survivors(S, q, K, valid, make_key(d, i * W + j));
-                    }
-#pragma unroll
-                    for (int q = 0; q < Q; ++q)
-                        if (q < nq) tauhi[q] = (uint32_t)(S.tau[q] >> 32);
-                }
-            }
-        }
+    // ---- query values
+    if (L < Q) {
+        const int qr = L / QC, qc = L % QC;
+        const bool ok = qr < nqr && qc < nqc;
+        S.iq[L] = ok ? pc1[(size_t)(r0 + qr) * W + c0 + qc] : qnan;
+        S.listn[L] = 0;
+        S.tau[L] = 0ull;
     }
-
-    // ---- final merge: list = top-K of each query
-    for (int q = 0; q < nq; ++q)
-        if (uni(S.cnt[q]) > 0) flush_query(S, q, K);
     wave_sync();
 
-    // ---- outputs: neighbour lists
-    const int npx = H * W;
-    for (int q = 0; q < nq; ++q) {
-        const size_t pix = (size_t)(r0 + q) * W + c;
-        const uint64_t key = S.list[q][L];
-        if (L < K) {
-            if (f.out_nbr) f.out_nbr[pix * K + L] = (int32_t)(uint32_t)key;
-            if (f.out_dist) f.out_dist[pix * K + L] = __uint_as_float((uint32_t)(key >> 32));
+    // ---- pass A.  The K-th smallest distance d_K of a compact block bounds
+    // the query's final K-th key from above by (d_K, max index).  All block
+    // loads are issued first, then one 64-lane sort of the distance bits per
+    // query.
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int qr = q / QC, qc = q % QC;
+        if (qr < nqr && qc < nqc) {
+            const int r = r0 + qr, c = c0 + qc;
+            int i, j;
+            uint32_t db = 0xffffffffu;
+            if (block_cand(f, r, c, L, i, j)) {
+                const float a = feat(lam, r) - feat(lam, i);
+                const float b = feat(lam, c) - feat(lam, j);
+                const float e = S.iq[q] - pc1[(size_t)i * W + j];
+                db = __float_as_uint(fmaf(e, e, fmaf(b, b, a * a)));
+            }
+            S.list[q][L] = db;
+        }
+    }
+    wave_sync();
+    for (int q = 0; q < Q; ++q) {
+        const int qr = q / QC, qc = q % QC;
+        if (qr < nqr && qc < nqc) {
+            const uint32_t v = sort64_u32(S.list[q][L]);
+            const uint32_t dk = uniu(xlane_read(v, K - 1));
+            if (L == 0) S.tau[q] = ((uint64_t)dk << 32) | 0xffffffffull;
+        }
+    }
+    wave_sync();
+    if (L < Q) S.tauhi[L] = (uint32_t)(S.tau[L] >> 32);
+    wave_sync();
+
+    // Uniform per-query values live in VGPRs (read from LDS) to keep the
+    // scalar register file free for loop state.  Queries off the frame have
+    // iq = NaN and bound 0, so they never pass the test below.
+    float iq[Q];
+    uint32_t th[Q];
+    int cnt[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        iq[q] = S.iq[q];
+        th[q] = S.tauhi[q];
+        cnt[q] = 0;
+    }
+
+    // ---- pass B: window rows x 64-column chunks, nearest chunk first
+    const int rlo = max(0, r0 - R);
+    const int rhi = min(H - 1, r0 + nqr - 1 + R);
+    const int nch = (W + WAVE - 1) / WAVE;
+    const int cc = (c0 + (nqc - 1) / 2) / WAVE;
+    bool right_alive = true, left_alive = true;
+
+    for (int t = 0; t < 2 * nch; ++t) {
+        const int m = (t & 1) ? cc + (t + 1) / 2 : cc - t / 2;
+        if (m < 0 || m >= nch) continue;
+        if ((m > cc && !right_alive) || (m < cc && !left_alive)) continue;
+        const int J = m * WAVE;
+        const int j = J + L;
+        const bool valid = j < W;
+        const int jl = valid ? j : W - 1;
+        float b[QC];
+#pragma unroll
+        for (int qc = 0; qc < QC; ++qc) b[qc] = feat(lam, c0 + qc) - feat(lam, j);
+
+        int lo = rlo, hi = rhi;
+        if (PRUNE) {
+            // Lower bound of Eq. 1 over the chunk for each query: the column
+            // term at the chunk column nearest the query plus the row term of
+            // the row; the spectral term is >= 0 and rounding is monotone.
+            // Keep the rows where some query could still reach its bound.
+            const int Je = min(J + WAVE - 1, W - 1);
+            float bmin[QC];
+#pragma unroll
+            for (int qc = 0; qc < QC; ++qc) {
+                const int cq = c0 + qc;
+                const int jn = cq < J ? J : (cq > Je ? Je : cq);
+                bmin[qc] = feat(lam, cq) - feat(lam, jn);
+            }
+            int nlo = 0x7fffffff, nhi = -1;
+            for (int base = rlo; base <= rhi; base += WAVE) {
+                const int i = base + L;
+                const float fi = feat(lam, i);
+                bool live = false;
+#pragma unroll
+                for (int qr = 0; qr < QR; ++qr) {
+                    const int r = r0 + qr;
+                    const float a = feat(lam, r) - fi;
+                    const float a2 = a * a;
+                    const bool inwin = qr < nqr && i <= rhi && i >= r - R && i <= r + R;
+#pragma unroll
+                    for (int qc = 0; qc < QC; ++qc) {
+                        const uint32_t lb = __float_as_uint(fmaf(bmin[qc], bmin[qc], a2));
+                        live |= inwin && lb <= th[qr * QC + qc];
+                    }
+                }
+                const uint64_t msk = ballot(live);
+                if (msk) {
+                    nlo = min(nlo, base + (int)__builtin_ctzll(msk));
+                    nhi = max(nhi, base + 63 - (int)__builtin_clzll(msk));
+                }
+            }
+            if (nhi < 0) {
+                // no query can gain here; chunks further out on this side have
+                // larger column terms for every query
+                if (m > cc) right_alive = false;
+                if (m < cc) left_alive = false;
+                continue;
+            }
+            lo = nlo;
+            hi = nhi;
+        }
+
+        for (int blk = lo; blk <= hi; blk += A2ROWS) {
+            // a2 table for rows blk .. blk+A2ROWS-1; +inf marks a row outside
+            // a query row's window (or past hi), so d = +inf there.
+            wave_sync();
+            for (int u = L; u < A2ROWS * QR; u += WAVE) {
+                const int rr = u / QR, qr = u % QR;
+                const int r = r0 + qr, i = blk + rr;
+                const bool act = qr < nqr && i <= hi && i >= r - R && i <= r + R;
+                const float a = feat(lam, r) - feat(lam, i);
+                S.a2t[rr][qr] = act ? a * a : pinf;
+            }
+            wave_sync();
+            const int nb = min(A2ROWS, hi - blk + 1);
+            float ipn[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) ipn[u] = pc1[(size_t)min(blk + u, hi) * W + jl];
+            for (int g = 0; g < nb; g += 4) {
+                float ip[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) ip[u] = valid ? ipn[u] : qnan;
+                if (g + 4 < nb) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        ipn[u] = pc1[(size_t)min(blk + g + 4 + u, hi) * W + jl];
+                }
+                float a2[4][QR];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int qr = 0; qr < QR; ++qr) a2[u][qr] = S.a2t[g + u][qr];
+                const int i0 = blk + g;
+                uint32_t ovf = 0;  // queries whose pending buffer could not take a row
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const int qr = q / QC, qc = q % QC;
+                    float d[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const float e = iq[q] - ip[u];
+                        const float tt = fmaf(b[qc], b[qc], a2[u][qr]);
+                        d[u] = fmaf(e, e, tt);
+                    }
+                    const uint32_t mn = min(min(__float_as_uint(d[0]), __float_as_uint(d[1])),
+                                            min(__float_as_uint(d[2]), __float_as_uint(d[3])));
+                    if (ballot(mn <= th[q])) {
+                        // rare: append the candidates with key <= tau while they fit
+                        const uint64_t tq = S.tau[q];
+                        const int r = r0 + qr;
+                        bool stop = false;
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int i = i0 + u;
+                            if (stop || qr >= nqr || i > hi || i < r - R || i > r + R) continue;
+                            const int idx = i * W + j;
+                            const bool ok = valid && make_key(d[u], idx) <= tq;
+                            const uint64_t msk = ballot(ok);
+                            if (msk) {
+                                const int n = __builtin_popcountll(msk);
+                                if (cnt[q] + n > WAVE) {
+                                    stop = true;
+                                    ovf |= 1u << q;
+                                    if (L == 0) S.ovu[q] = u;
+                                } else {
+                                    if (ok) S.pend[q][cnt[q] + mbcnt(msk)] = make_key(d[u], idx);
+                                    cnt[q] += n;
+                                }
+                            }
+                        }
+                    }
+                }
+                if (ovf) {
+                    // rare: merge the full buffers, then append the rest of the group
+#pragma unroll
+                    for (int q = 0; q < Q; ++q)
+                        if (L == 0) S.cnt[q] = cnt[q];
+                    wave_sync();
+                    while (ovf) {
+                        const int q = __builtin_ctz(ovf);
+                        ovf &= ovf - 1;
+                        const int qr = q / QC, qc = q % QC;
+                        const int r = r0 + qr;
+                        int cq = uni(S.cnt[q]);
+                        uint64_t tq = uni64(S.tau[q]);
+                        const int u0 = uni(S.ovu[q]);
+                        const float bq = feat(lam, c0 + qc) - feat(lam, j);
+                        const float iqq = S.iq[q];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int i = i0 + u;
+                            if (u < u0 || i > hi || i < r - R || i > r + R) continue;
+                            const float a2q = S.a2t[g + u][qr];
+                            const float e = iqq - ip[u];
+                            const float du = fmaf(e, e, fmaf(bq, bq, a2q));
+                            const int idx = i * W + j;
+                            bool ok = valid && make_key(du, idx) <= tq;
+                            uint64_t msk = ballot(ok);
+                            if (!msk) continue;
+                            int n = __builtin_popcountll(msk);
+                            if (cq + n > WAVE) {
+                                const uint64_t nb2 = flush_query(S, f, r0, c0, q, cq, false);
+                                cq = 0;
+                                tq = nb2 < tq ? nb2 : tq;
+                                ok = valid && make_key(du, idx) <= tq;
+                                msk = ballot(ok);
+                                n = __builtin_popcountll(msk);
+                            }
+                            if (ok) S.pend[q][cq + mbcnt(msk)] = make_key(du, idx);
+                            cq += n;
+                        }
+                        wave_sync();
+                        if (L == 0) {
+                            S.cnt[q] = cq;
+                            S.tau[q] = tq;
+                            S.tauhi[q] = (uint32_t)(tq >> 32);
+                        }
+                        wave_sync();
+                    }
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) {
+                        cnt[q] = uni(S.cnt[q]);
+                        th[q] = S.tauhi[q];
+                    }
+                }
+            }
         }
     }
 
+    // ---- final merge per query; neighbour outputs
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+        if (L == 0) S.cnt[q] = cnt[q];
+    wave_sync();
+    for (int q = 0; q < Q; ++q) {
+        const int qr = q / QC, qc = q % QC;
+        if (qr < nqr && qc < nqc) flush_query(S, f, r0, c0, q, uni(S.cnt[q]), true);
+    }
+    wave_sync();
+
     // ---- Eq. 2: sums in neighbour order, one lane per (query, class)
+    const int npx = H * W;
     const float* __restrict__ prob = f.prob;
-    for (int p = L; p < nq * C; p += WAVE) {
+    for (int p = L; p < Q * C; p += WAVE) {
         const int q = p / C, cl = p - q * C;
+        const int qr = q / QC, qc = q % QC;
+        if (qr >= nqr || qc >= nqc) continue;
         float s = 0.0f;
-        for (int k = 0; k < K; ++k) {
-            const uint32_t idx = (uint32_t)S.list[q][k];
-            if (idx < (uint32_t)npx) s = s + prob[(size_t)idx * C + cl];
+        for (int k0 = 0; k0 < K; k0 += 8) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const uint32_t idx = (k0 + u < K) ? S.list[q][k0 + u] : 0xffffffffu;
+                v[u] = idx < (uint32_t)npx ? prob[(size_t)idx * C + cl] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (k0 + u < K) s = s + v[u];
         }
         S.sums[q][cl] = s;
-        const size_t pix = (size_t)(r0 + q) * W + c;
+        const size_t pix = (size_t)(r0 + qr) * W + c0 + qc;
         f.out_prob[pix * C + cl] = s / (float)K;
     }
     wave_sync();
-    if (L < nq) {
-        int best = 0;
-        float bs = S.sums[L][0];
-        for (int cl = 1; cl < C; ++cl) {
-            const float v = S.sums[L][cl];
-            if (v > bs) { bs = v; best = cl; }
+    if (L < Q) {
+        const int qr = L / QC, qc = L % QC;
+        if (qr < nqr && qc < nqc) {
+            int best = 0;
+            float bs = S.sums[L][0];
+            for (int cl = 1; cl < C; ++cl) {
+                const float v = S.sums[L][cl];
+                if (v > bs) { bs = v; best = cl; }
+            }
+            f.out_class[(size_t)(r0 + qr) * W + c0 + qc] = best;
         }
-        f.out_class[(size_t)(r0 + L) * W + c] = best;
     }
     wave_sync();
 }
@@ -358,27 +591,28 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     return (b & 7) * per + (b >> 3);
 }
 
-template <int Q, int WPB, bool PRUNE>
+template <int QR, int QC, int WPB, bool PRUNE>
 __global__ void __launch_bounds__(WPB * WAVE) filter_frame_kernel(FrameDesc f) {
-    __shared__ WaveState<Q> lds[WPB];
+    __shared__ TileState<QR, QC> lds[WPB];
     const int w = uni((int)(threadIdx.x >> 6));
     const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    const int strips_per_col = (f.H + Q - 1) / Q;
+    const int ntc = (f.W + QC - 1) / QC;
+    const long long ntiles = (long long)((f.H + QR - 1) / QR) * ntc;
     const long long s = (long long)b * WPB + w;
-    if (s >= (long long)strips_per_col * f.W) return;
-    const int band = (int)(s / f.W);
-    const int c = (int)(s - (long long)band * f.W);
-    process_strip<Q, PRUNE>(lds[w], f, c, band * Q);
+    if (s >= ntiles) return;
+    const int band = (int)(s / ntc);
+    const int tc = (int)(s - (long long)band * ntc);
+    process_tile<QR, QC, PRUNE>(lds[w], f, band * QR, tc * QC);
 }
 
-// Persistent batched kernel: each wavefront claims strip tasks from a global
+// Persistent batched kernel: each wavefront claims tile tasks from a global
 // counter until all tasks of all frames are taken.  Every wavefront leaves the
 // loop after one failed claim, so the grid always drains.
-template <int Q, int WPB, bool PRUNE>
+template <int QR, int QC, int WPB, bool PRUNE>
 __global__ void __launch_bounds__(WPB * WAVE)
 filter_batch_kernel(const FrameDesc* __restrict__ frames, const uint32_t* __restrict__ task_start,
                     uint32_t nframes, uint32_t total_tasks, uint32_t* counter) {
-    __shared__ WaveState<Q> lds[WPB];
+    __shared__ TileState<QR, QC> lds[WPB];
     const int w = uni((int)(threadIdx.x >> 6));
     const int L = lane_id();
     for (;;) {
@@ -394,52 +628,60 @@ filter_batch_kernel(const FrameDesc* __restrict__ frames, const uint32_t* __rest
         }
         const FrameDesc f = frames[lo];
         const uint32_t s = t - task_start[lo];
-        const int band = (int)(s / (uint32_t)f.W);
-        const int c = (int)(s - (uint32_t)band * (uint32_t)f.W);
-        process_strip<Q, PRUNE>(lds[w], f, c, band * Q);
+        const uint32_t ntc = (uint32_t)((f.W + QC - 1) / QC);
+        const int band = (int)(s / ntc);
+        const int tc = (int)(s - (uint32_t)band * ntc);
+        process_tile<QR, QC, PRUNE>(lds[w], f, band * QR, tc * QC);
     }
 }
 
-template <int Q, int WPB, bool PRUNE>
+template <int QR, int QC, int WPB, bool PRUNE>
 int launch_frame_t(const FrameDesc& f, hipStream_t st) {
-    const long long strips = (long long)((f.H + Q - 1) / Q) * f.W;
-    const long long blocks = (strips + WPB - 1) / WPB;
-    hipLaunchKernelGGL((filter_frame_kernel<Q, WPB, PRUNE>), dim3((unsigned)blocks),
+    const long long tiles = (long long)((f.H + QR - 1) / QR) * ((f.W + QC - 1) / QC);
+    const long long blocks = (tiles + WPB - 1) / WPB;
+    hipLaunchKernelGGL((filter_frame_kernel<QR, QC, WPB, PRUNE>), dim3((unsigned)blocks),
                        dim3(WPB * WAVE), 0, st, f);
     return (int)hipGetLastError();
 }
 
-template <int Q, int WPB, bool PRUNE>
+template <int QR, int QC, int WPB, bool PRUNE>
 int launch_batch_t(const FrameDesc* fr, const uint32_t* ts, uint32_t n, uint32_t tot,
                    uint32_t* ctr, int grid, hipStream_t st) {
-    hipLaunchKernelGGL((filter_batch_kernel<Q, WPB, PRUNE>), dim3((unsigned)grid),
+    hipLaunchKernelGGL((filter_batch_kernel<QR, QC, WPB, PRUNE>), dim3((unsigned)grid),
                        dim3(WPB * WAVE), 0, st, fr, ts, n, tot, ctr);
     return (int)hipGetLastError();
 }
 
-template <int Q, int WPB, bool PRUNE>
+template <int QR, int QC, int WPB, bool PRUNE>
 int occupancy_t() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, filter_batch_kernel<Q, WPB, PRUNE>,
-                                                     WPB * WAVE, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, filter_batch_kernel<QR, QC, WPB, PRUNE>, WPB * WAVE, 0) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
 
-#define KNNF_DISPATCH(FN, ...)                                                         \
-    do {                                                                               \
-        const bool pr = cfg.pruned != 0;                                               \
-        switch (cfg.queries * 16 + cfg.waves) {                                        \
-        case 4 * 16 + 1: return pr ? FN<4, 1, true>(__VA_ARGS__) : FN<4, 1, false>(__VA_ARGS__);   \
-        case 4 * 16 + 2: return pr ? FN<4, 2, true>(__VA_ARGS__) : FN<4, 2, false>(__VA_ARGS__);   \
-        case 4 * 16 + 4: return pr ? FN<4, 4, true>(__VA_ARGS__) : FN<4, 4, false>(__VA_ARGS__);   \
-        case 8 * 16 + 1: return pr ? FN<8, 1, true>(__VA_ARGS__) : FN<8, 1, false>(__VA_ARGS__);   \
-        case 8 * 16 + 2: return pr ? FN<8, 2, true>(__VA_ARGS__) : FN<8, 2, false>(__VA_ARGS__);   \
-        case 8 * 16 + 4: return pr ? FN<8, 4, true>(__VA_ARGS__) : FN<8, 4, false>(__VA_ARGS__);   \
-        case 16 * 16 + 1: return pr ? FN<16, 1, true>(__VA_ARGS__) : FN<16, 1, false>(__VA_ARGS__); \
-        case 16 * 16 + 2: return pr ? FN<16, 2, true>(__VA_ARGS__) : FN<16, 2, false>(__VA_ARGS__); \
-        default: return (int)hipErrorInvalidValue;                                     \
-        }                                                                              \
+// Supported tile shapes (rows x columns) and workgroup sizes.
+#define KNNF_SHAPE(FN, QR, QC, ...)                                                        \
+    case (QR) * 10000 + (QC) * 100 + 1:                                                    \
+        return pr ? FN<QR, QC, 1, true>(__VA_ARGS__) : FN<QR, QC, 1, false>(__VA_ARGS__);  \
+    case (QR) * 10000 + (QC) * 100 + 2:                                                    \
+        return pr ? FN<QR, QC, 2, true>(__VA_ARGS__) : FN<QR, QC, 2, false>(__VA_ARGS__);  \
+    case (QR) * 10000 + (QC) * 100 + 4:                                                    \
+        return pr ? FN<QR, QC, 4, true>(__VA_ARGS__) : FN<QR, QC, 4, false>(__VA_ARGS__);
+
+#define KNNF_DISPATCH(FN, ...)                                                  \
+    do {                                                                        \
+        const bool pr = cfg.pruned != 0;                                        \
+        switch (cfg.rows * 10000 + cfg.cols * 100 + cfg.waves) {                \
+            KNNF_SHAPE(FN, 1, 8, __VA_ARGS__)                                   \
+            KNNF_SHAPE(FN, 1, 16, __VA_ARGS__)                                  \
+            KNNF_SHAPE(FN, 2, 4, __VA_ARGS__)                                   \
+            KNNF_SHAPE(FN, 2, 8, __VA_ARGS__)                                   \
+            KNNF_SHAPE(FN, 4, 4, __VA_ARGS__)                                   \
+        default:                                                                \
+            return (int)hipErrorInvalidValue;                                   \
+        }                                                                       \
     } while (0)
 
 }  // namespace

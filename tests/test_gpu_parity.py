@@ -19,10 +19,15 @@ pytestmark = pytest.mark.gpu
 
 PROB_TOL = 1e-6
 
-EXH8 = dict(search=0, queries=8, waves=2)
-PRU8 = dict(search=1, queries=8, waves=2)
-ALL_PLANS = [dict(search=s, queries=q, waves=w)
-             for s in (0, 1) for q in (4, 8, 16) for w in (1, 2, 4) if not (q == 16 and w == 4)]
+SHAPES = [(1, 8), (1, 16), (2, 4), (2, 8), (4, 4)]
+EXH8 = dict(search=0, tile_rows=2, tile_cols=8, waves=2)
+PRU8 = dict(search=1, tile_rows=2, tile_cols=8, waves=2)
+ALL_PLANS = [dict(search=s, tile_rows=r, tile_cols=c, waves=w)
+             for s in (0, 1) for (r, c) in SHAPES for w in (1, 2, 4)]
+
+
+def plan_id(p):
+    return f"s{p['search']}t{p['tile_rows']}x{p['tile_cols']}w{p['waves']}"
 
 
 def say(msg):
@@ -79,9 +84,10 @@ CASES = [
 
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: c[0])
-@pytest.mark.parametrize("plan", [EXH8, PRU8, dict(search=1, queries=4, waves=4),
-                                  dict(search=0, queries=16, waves=1)],
-                         ids=lambda p: f"s{p['search']}q{p['queries']}w{p['waves']}")
+@pytest.mark.parametrize("plan", [EXH8, PRU8, dict(search=1, tile_rows=4, tile_cols=4, waves=4),
+                                  dict(search=0, tile_rows=1, tile_cols=16, waves=1),
+                                  dict(search=1, tile_rows=1, tile_cols=8, waves=1)],
+                         ids=plan_id)
 def test_small_frames_bit_exact(ctx, case, plan):
     label, gen, H, W, K, R, lam = case
     pc1, prob = inputs.GENERATORS[gen](H, W, 31)
@@ -90,7 +96,7 @@ def test_small_frames_bit_exact(ctx, case, plan):
     assert_parity(run_gpu(ctx, pc1, prob, K, R, lam, plan), ref, label)
 
 
-@pytest.mark.parametrize("plan", ALL_PLANS, ids=lambda p: f"s{p['search']}q{p['queries']}w{p['waves']}")
+@pytest.mark.parametrize("plan", ALL_PLANS, ids=plan_id)
 def test_config0_all_plans(ctx, plan):
     """One 64 x 64 uniform frame, K = 8, +-4 rows, lambda = 0.01, seed 0."""
     spec = inputs.config0().frames[0]
@@ -186,7 +192,7 @@ def test_batch_matches_single_frames_and_oracle(ctx):
              inputs.FrameSpec("brain", 130, 61, 5, K=40, R=14),
              inputs.FrameSpec("unif", 1, 1, 6, K=1, R=0),
              inputs.FrameSpec("brain", 64, 64, 7, K=24, R=3, lam=0.05)]
-    for plan in (EXH8, PRU8, dict(search=1, queries=16, waves=1)):
+    for plan in (EXH8, PRU8, dict(search=1, tile_rows=1, tile_cols=16, waves=1)):
         say(f"batch of {len(specs)} plan={plan}")
         data = [s.make() for s in specs]
         batch = [DeviceFrame(p, q, s.K, s.R, s.lam) for s, (p, q) in zip(specs, data)]
