@@ -70,10 +70,11 @@ typedef enum {
 /* Parameter limits checked by every filtering call. */
 #define KNNF_MAX_K 64
 #define KNNF_MAX_C 16
+#define KNNF_MAX_SIDE 16777216 /* 2^24: larger row/column numbers are not exact in binary32 */
 
 /*
  * One frame: sizes, filter parameters and device pointers.
- *   H, W    >= 1, H*W <= 2^31 - 1
+ *   H, W    1..KNNF_MAX_SIDE, H*W <= 2^31 - 1
  *   C       number of classes, 1..KNNF_MAX_C          (Sec. II.C.1, Eq. 2)
  *   K       neighbours, 1..KNNF_MAX_K and no larger than the smallest window,
  *           min(H, R+1) * W (the paper leaves K > window size undefined)
@@ -114,7 +115,9 @@ typedef enum { KNNF_SEARCH_EXHAUSTIVE = 0, KNNF_SEARCH_PRUNED = 1 } knnf_search;
  *   tile_rows     query pixels per wavefront task = tile_rows x tile_cols;
  *   tile_cols     supported tiles (rows x cols): 1x8, 1x16, 2x4, 2x8, 4x4
  *   waves         wavefronts per workgroup; 1, 2 or 4
- * A zero field means "the context's default".  search = 0 is exhaustive.
+ * A zero tile or wave field means "the context's default" (initially a pruned
+ * search with 2 x 4 tiles and one wavefront per workgroup); search is always
+ * taken from the plan (0 = exhaustive).
  */
 typedef struct {
     int32_t search;

@@ -68,6 +68,7 @@ static int cand_cmp(const void* pa, const void* pb) {
 /* Parameter rules shared by every entry point of this file. */
 static int check_params(int H, int W, int C, int K, int R, float lambda) {
     if (H < 1 || W < 1) return ORC_EINVAL;
+    if (H > (1 << 24) || W > (1 << 24)) return ORC_EINVAL; /* coordinates exact in binary32 */
     if ((int64_t)H * (int64_t)W > (int64_t)INT32_MAX) return ORC_EINVAL;
     if (C < 1 || C > 16) return ORC_EINVAL;
     if (R < 0) return ORC_EINVAL;

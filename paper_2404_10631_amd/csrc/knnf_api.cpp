@@ -75,10 +75,10 @@ namespace {
 
 knnf_plan default_plan() {
     knnf_plan p{};
-    p.search = KNNF_SEARCH_EXHAUSTIVE;
+    p.search = KNNF_SEARCH_PRUNED;
     p.tile_rows = 2;
-    p.tile_cols = 8;
-    p.waves = 2;
+    p.tile_cols = 4;
+    p.waves = 1;
     return p;
 }
 
@@ -134,6 +134,8 @@ knnf_status validate(const knnf_frame* f, int index) {
     if (!f) return fail(KNNF_EINVAL, "frame %d: NULL frame", index);
     if (f->H < 1 || f->W < 1)
         return fail(KNNF_EINVAL, "frame %d: H=%d W=%d must be >= 1", index, f->H, f->W);
+    if (f->H > KNNF_MAX_SIDE || f->W > KNNF_MAX_SIDE)
+        return fail(KNNF_EINVAL, "frame %d: H or W exceeds %d", index, KNNF_MAX_SIDE);
     if ((int64_t)f->H * f->W > 0x7fffffffLL)
         return fail(KNNF_EINVAL, "frame %d: H*W exceeds 2^31-1", index);
     if (f->C < 1 || f->C > KNNF_MAX_C)

@@ -48,7 +48,8 @@ namespace {
 
 constexpr uint64_t KEY_INF = ~0ull;
 constexpr int WAVE = 64;
-constexpr int A2ROWS = 32;  // window rows per block of the LDS a2 table
+constexpr int A2ROWS = 64;  // window rows per block of the LDS a2 table
+constexpr int A2PAD = 4;    // padding rows (+inf) so a 4-row group may start anywhere
 constexpr int MAXC = 16;
 
 __device__ __forceinline__ int lane_id() {
@@ -177,6 +178,97 @@ __device__ __forceinline__ uint32_t sort64_u32(uint32_t v) {
     return v;
 }
 
+// ---- segmented sorts: the Q queries of a tile sorted together.  Segment q
+// (64 elements) lives in lanes q*P .. q*P+P-1, P = 64 / E; lane L holds
+// elements e = (L % P) * E + r in x[r], r < E.  Partners e ^ d with d < E are
+// in the same lane (register pairs, no exchange); d >= E are in lane L ^ (d/E).
+template <int J>
+__device__ __forceinline__ uint64_t xlane64(uint64_t v) {
+    return ((uint64_t)xlane<J>((uint32_t)(v >> 32)) << 32) | (uint64_t)xlane<J>((uint32_t)v);
+}
+
+template <int E, int K_, int D>
+__device__ __forceinline__ void seg_step_key(uint64_t (&x)[E], int lp) {
+    if constexpr (D < E) {
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            if (r & D) continue;
+            // elements lp*E + r and lp*E + (r|D); descending block if bit K_ is set
+            const bool desc = (K_ < WAVE) && (((lp * E + r) & K_) != 0);
+            const uint64_t a = x[r], b = x[r | D];
+            const bool sw = (b < a) != desc;
+            x[r] = sw ? b : a;
+            x[r | D] = sw ? a : b;
+        }
+    } else {
+        constexpr int LD = D / E;
+        const bool upper = (lp & LD) != 0;
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const bool desc = (K_ < WAVE) && (((lp * E + r) & K_) != 0);
+            const uint64_t p = xlane64<LD>(x[r]);
+            const bool take = (p < x[r]) != (upper != desc);
+            x[r] = take ? p : x[r];
+        }
+    }
+}
+
+template <int E, int K_, int D>
+__device__ __forceinline__ void seg_stage_key(uint64_t (&x)[E], int lp) {
+    seg_step_key<E, K_, D>(x, lp);
+    if constexpr (D > 1) seg_stage_key<E, K_, D / 2>(x, lp);
+}
+
+template <int E>
+__device__ __forceinline__ void seg_sort_key(uint64_t (&x)[E], int lp) {
+    seg_stage_key<E, 2, 1>(x, lp);
+    seg_stage_key<E, 4, 2>(x, lp);
+    seg_stage_key<E, 8, 4>(x, lp);
+    seg_stage_key<E, 16, 8>(x, lp);
+    seg_stage_key<E, 32, 16>(x, lp);
+    seg_stage_key<E, 64, 32>(x, lp);
+}
+
+template <int E, int K_, int D>
+__device__ __forceinline__ void seg_step_u32(uint32_t (&x)[E], int lp) {
+    if constexpr (D < E) {
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            if (r & D) continue;
+            const bool desc = (K_ < WAVE) && (((lp * E + r) & K_) != 0);
+            const uint32_t a = x[r], b = x[r | D];
+            const uint32_t lo = min(a, b), hi = max(a, b);
+            x[r] = desc ? hi : lo;
+            x[r | D] = desc ? lo : hi;
+        }
+    } else {
+        constexpr int LD = D / E;
+        const bool upper = (lp & LD) != 0;
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const bool desc = (K_ < WAVE) && (((lp * E + r) & K_) != 0);
+            const uint32_t p = xlane<LD>(x[r]);
+            x[r] = (upper != desc) ? max(x[r], p) : min(x[r], p);
+        }
+    }
+}
+
+template <int E, int K_, int D>
+__device__ __forceinline__ void seg_stage_u32(uint32_t (&x)[E], int lp) {
+    seg_step_u32<E, K_, D>(x, lp);
+    if constexpr (D > 1) seg_stage_u32<E, K_, D / 2>(x, lp);
+}
+
+template <int E>
+__device__ __forceinline__ void seg_sort_u32(uint32_t (&x)[E], int lp) {
+    seg_stage_u32<E, 2, 1>(x, lp);
+    seg_stage_u32<E, 4, 2>(x, lp);
+    seg_stage_u32<E, 8, 4>(x, lp);
+    seg_stage_u32<E, 16, 8>(x, lp);
+    seg_stage_u32<E, 32, 16>(x, lp);
+    seg_stage_u32<E, 64, 32>(x, lp);
+}
+
 // Per-wavefront LDS state of one tile of QR x QC query pixels.
 template <int QR, int QC>
 struct alignas(16) TileState {
@@ -187,11 +279,10 @@ struct alignas(16) TileState {
     float sums[Q][MAXC];      // class sums for the argmax
     uint64_t tau[Q];          // current bound on the K-th key of each query
     uint32_t tauhi[Q];        // its distance bits (high word)
-    float a2t[A2ROWS][QR];    // fl32(a*a) for a block of window rows (+inf: inactive)
+    float a2t[A2ROWS + A2PAD][QR];  // fl32(a*a) for a block of window rows (+inf: inactive)
     float iq[Q];              // I of each query pixel (NaN for pixels off the frame)
     int listn[Q];             // valid list entries (<= K)
     int cnt[Q];               // pending entries (mirror of the scan's registers)
-    int ovu[Q];               // first row of the group not yet appended (overflow)
 };
 
 // Coordinate feature fr(x) = fl32(lambda * (float)x).
@@ -292,37 +383,51 @@ __device__ __forceinline__ void process_tile(TileState<QR, QC>& S, const FrameDe
     wave_sync();
 
     // ---- pass A.  The K-th smallest distance d_K of a compact block bounds
-    // the query's final K-th key from above by (d_K, max index).  All block
-    // loads are issued first, then one 64-lane sort of the distance bits per
-    // query.
+    // the query's final K-th key from above by (d_K, max index).  All Q
+    // blocks are evaluated and sorted together: segment q of the wavefront
+    // holds query q's 64 block candidates, Q per lane.
+    constexpr int E = Q, P = WAVE / Q;
+    const int sq = L / P, lp = L % P;  // this lane's query (segment) and slot in it
+    const int sqr = sq / QC, sqc = sq % QC;
+    const bool sok = sqr < nqr && sqc < nqc;
+    {
+        const int r = r0 + sqr, c = c0 + sqc;
+        const int i0w = max(0, r - R), i1w = min(H - 1, r + R);
+        const int nr = i1w - i0w + 1;
+        const int lbr = nr >= 8 ? 3 : (nr >= 4 ? 2 : (nr >= 2 ? 1 : 0));
+        const int br = 1 << lbr;
+        const int lbc = 6 - lbr;
+        const int bc = 1 << lbc;
+        const int rb = min(max(r - br / 2, i0w), i1w - br + 1);
+        const int cb = max(0, min(c - bc / 2, W - bc));
+        const float iqs = S.iq[sq];
+        const float frq = feat(lam, r), fcq = feat(lam, c);
+        uint32_t x[E];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const int qr = q / QC, qc = q % QC;
-        if (qr < nqr && qc < nqc) {
-            const int r = r0 + qr, c = c0 + qc;
-            int i, j;
-            uint32_t db = 0xffffffffu;
-            if (block_cand(f, r, c, L, i, j)) {
-                const float a = feat(lam, r) - feat(lam, i);
-                const float b = feat(lam, c) - feat(lam, j);
-                const float e = S.iq[q] - pc1[(size_t)i * W + j];
-                db = __float_as_uint(fmaf(e, e, fmaf(b, b, a * a)));
+        for (int u = 0; u < E; ++u) {
+            const int e = lp * E + u;
+            const int i = rb + (e >> lbc);
+            const int j = cb + (e & (bc - 1));
+            x[u] = 0xffffffffu;
+            if (sok && j < W) {
+                const float a = frq - feat(lam, i);
+                const float b = fcq - feat(lam, j);
+                const float ee = iqs - pc1[(size_t)i * W + j];
+                x[u] = __float_as_uint(fmaf(ee, ee, fmaf(b, b, a * a)));
             }
-            S.list[q][L] = db;
         }
-    }
-    wave_sync();
-    for (int q = 0; q < Q; ++q) {
-        const int qr = q / QC, qc = q % QC;
-        if (qr < nqr && qc < nqc) {
-            const uint32_t v = sort64_u32(S.list[q][L]);
-            const uint32_t dk = uniu(xlane_read(v, K - 1));
-            if (L == 0) S.tau[q] = ((uint64_t)dk << 32) | 0xffffffffull;
+        seg_sort_u32<E>(x, lp);
+#pragma unroll
+        for (int u = 0; u < E; ++u) S.list[sq][lp * E + u] = x[u];
+        wave_sync();
+        if (L < Q) {
+            const bool ok = (L / QC) < nqr && (L % QC) < nqc;
+            const uint32_t dk = S.list[L][K - 1];
+            S.tau[L] = ok ? (((uint64_t)dk << 32) | 0xffffffffull) : 0ull;
+            S.tauhi[L] = ok ? dk : 0u;
         }
+        wave_sync();
     }
-    wave_sync();
-    if (L < Q) S.tauhi[L] = (uint32_t)(S.tau[L] >> 32);
-    wave_sync();
 
     // Uniform per-query values live in VGPRs (read from LDS) to keep the
     // scalar register file free for loop state.  Queries off the frame have
@@ -343,6 +448,8 @@ __device__ __forceinline__ void process_tile(TileState<QR, QC>& S, const FrameDe
     const int nch = (W + WAVE - 1) / WAVE;
     const int cc = (c0 + (nqc - 1) / 2) / WAVE;
     bool right_alive = true, left_alive = true;
+    int tab_base = -1;       // first row of the a2 table contents
+    uint32_t exact = 0;      // queries whose bound carries a real index (after a merge)
 
     for (int t = 0; t < 2 * nch; ++t) {
         const int m = (t & 1) ? cc + (t + 1) / 2 : cc - t / 2;
@@ -352,9 +459,11 @@ __device__ __forceinline__ void process_tile(TileState<QR, QC>& S, const FrameDe
         const int j = J + L;
         const bool valid = j < W;
         const int jl = valid ? j : W - 1;
+        // lanes past the right edge get b = +inf, so every distance there is
+        // +inf (never below a finite bound; the append step checks `valid`)
         float b[QC];
 #pragma unroll
-        for (int qc = 0; qc < QC; ++qc) b[qc] = feat(lam, c0 + qc) - feat(lam, j);
+        for (int qc = 0; qc < QC; ++qc) b[qc] = valid ? feat(lam, c0 + qc) - feat(lam, j) : pinf;
 
         int lo = rlo, hi = rhi;
         if (PRUNE) {
@@ -383,8 +492,8 @@ __device__ __forceinline__ void process_tile(TileState<QR, QC>& S, const FrameDe
                     const bool inwin = qr < nqr && i <= rhi && i >= r - R && i <= r + R;
 #pragma unroll
                     for (int qc = 0; qc < QC; ++qc) {
-                        const uint32_t lb = __float_as_uint(fmaf(bmin[qc], bmin[qc], a2));
-                        live |= inwin && lb <= th[qr * QC + qc];
+                        const uint32_t lbd = __float_as_uint(fmaf(bmin[qc], bmin[qc], a2));
+                        live |= inwin && lbd <= th[qr * QC + qc];
                     }
                 }
                 const uint64_t msk = ballot(live);
@@ -404,30 +513,38 @@ __device__ __forceinline__ void process_tile(TileState<QR, QC>& S, const FrameDe
             hi = nhi;
         }
 
-        for (int blk = lo; blk <= hi; blk += A2ROWS) {
-            // a2 table for rows blk .. blk+A2ROWS-1; +inf marks a row outside
-            // a query row's window (or past hi), so d = +inf there.
-            wave_sync();
-            for (int u = L; u < A2ROWS * QR; u += WAVE) {
-                const int rr = u / QR, qr = u % QR;
-                const int r = r0 + qr, i = blk + rr;
-                const bool act = qr < nqr && i <= hi && i >= r - R && i <= r + R;
-                const float a = feat(lam, r) - feat(lam, i);
-                S.a2t[rr][qr] = act ? a * a : pinf;
+        // Table blocks are aligned to rlo: block k holds rows rlo + 64k ...
+        // rlo + 64k + 63 (+inf past rhi and in the padding), so windows of up
+        // to 64 rows fill it once per tile.
+        for (int blk = rlo + ((lo - rlo) / A2ROWS) * A2ROWS; blk <= hi; blk += A2ROWS) {
+            if (blk != tab_base) {
+                wave_sync();
+                for (int u = L; u < (A2ROWS + A2PAD) * QR; u += WAVE) {
+                    const int rr = u / QR, qr = u % QR;
+                    const int r = r0 + qr, i = blk + rr;
+                    const bool act = rr < A2ROWS && qr < nqr && i <= rhi && i >= r - R && i <= r + R;
+                    const float a = feat(lam, r) - feat(lam, i);
+                    S.a2t[rr][qr] = act ? a * a : pinf;
+                }
+                wave_sync();
+                tab_base = blk;
             }
-            wave_sync();
-            const int nb = min(A2ROWS, hi - blk + 1);
+            const int g0 = max(lo, blk) - blk;
+            const int g1 = min(hi, blk + A2ROWS - 1) - blk;  // last table row used
+            const uint32_t joff = (uint32_t)jl;
+            const float* __restrict__ rowp = pc1 + (size_t)(blk + g0) * W;
             float ipn[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) ipn[u] = pc1[(size_t)min(blk + u, hi) * W + jl];
-            for (int g = 0; g < nb; g += 4) {
+            for (int u = 0; u < 4; ++u)
+                ipn[u] = rowp[(size_t)min(u, g1 - g0) * W + joff];
+            for (int g = g0; g <= g1; g += 4) {
                 float ip[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) ip[u] = valid ? ipn[u] : qnan;
-                if (g + 4 < nb) {
+                for (int u = 0; u < 4; ++u) ip[u] = ipn[u];
+                if (g + 4 <= g1) {
+                    const float* __restrict__ np = pc1 + (size_t)(blk + g + 4) * W;
 #pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        ipn[u] = pc1[(size_t)min(blk + g + 4 + u, hi) * W + jl];
+                    for (int u = 0; u < 4; ++u) ipn[u] = np[(size_t)min(u, g1 - g - 4) * W + joff];
                 }
                 float a2[4][QR];
 #pragma unroll
@@ -449,37 +566,42 @@ __device__ __forceinline__ void process_tile(TileState<QR, QC>& S, const FrameDe
                     const uint32_t mn = min(min(__float_as_uint(d[0]), __float_as_uint(d[1])),
                                             min(__float_as_uint(d[2]), __float_as_uint(d[3])));
                     if (ballot(mn <= th[q])) {
-                        // rare: append the candidates with key <= tau while they fit
-                        const uint64_t tq = S.tau[q];
+                        // rare: some candidate of the group may belong to the
+                        // query.  Until the query's first merge its bound is
+                        // (d_K, max index), so key <= tau is d <= d_K; the
+                        // whole group is appended if it fits, otherwise (or
+                        // with an exact bound) the group goes to the merge path.
                         const int r = r0 + qr;
-                        bool stop = false;
+                        bool ok[4];
+                        uint64_t mu[4];
+                        int ntot = 0;
 #pragma unroll
                         for (int u = 0; u < 4; ++u) {
                             const int i = i0 + u;
-                            if (stop || qr >= nqr || i > hi || i < r - R || i > r + R) continue;
-                            const int idx = i * W + j;
-                            const bool ok = valid && make_key(d[u], idx) <= tq;
-                            const uint64_t msk = ballot(ok);
-                            if (msk) {
-                                const int n = __builtin_popcountll(msk);
-                                if (cnt[q] + n > WAVE) {
-                                    stop = true;
-                                    ovf |= 1u << q;
-                                    if (L == 0) S.ovu[q] = u;
-                                } else {
-                                    if (ok) S.pend[q][cnt[q] + mbcnt(msk)] = make_key(d[u], idx);
-                                    cnt[q] += n;
-                                }
+                            const bool rowok = i <= hi && i >= r - R && i <= r + R;
+                            ok[u] = valid && rowok && __float_as_uint(d[u]) <= th[q];
+                            mu[u] = ballot(ok[u]);
+                            ntot += __builtin_popcountll(mu[u]);
+                        }
+                        if (((exact >> q) & 1u) || cnt[q] + ntot > WAVE) {
+                            ovf |= 1u << q;
+                        } else {
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                if (ok[u])
+                                    S.pend[q][cnt[q] + mbcnt(mu[u])] = make_key(d[u], (i0 + u) * W + j);
+                                cnt[q] += __builtin_popcountll(mu[u]);
                             }
                         }
                     }
                 }
                 if (ovf) {
-                    // rare: merge the full buffers, then append the rest of the group
+                    // rare: merge full buffers and append the group exactly
 #pragma unroll
                     for (int q = 0; q < Q; ++q)
                         if (L == 0) S.cnt[q] = cnt[q];
                     wave_sync();
+                    exact |= ovf;
                     while (ovf) {
                         const int q = __builtin_ctz(ovf);
                         ovf &= ovf - 1;
@@ -487,13 +609,12 @@ __device__ __forceinline__ void process_tile(TileState<QR, QC>& S, const FrameDe
                         const int r = r0 + qr;
                         int cq = uni(S.cnt[q]);
                         uint64_t tq = uni64(S.tau[q]);
-                        const int u0 = uni(S.ovu[q]);
-                        const float bq = feat(lam, c0 + qc) - feat(lam, j);
+                        const float bq = valid ? feat(lam, c0 + qc) - feat(lam, j) : pinf;
                         const float iqq = S.iq[q];
 #pragma unroll
                         for (int u = 0; u < 4; ++u) {
                             const int i = i0 + u;
-                            if (u < u0 || i > hi || i < r - R || i > r + R) continue;
+                            if (i > hi || i < r - R || i > r + R) continue;
                             const float a2q = S.a2t[g + u][qr];
                             const float e = iqq - ip[u];
                             const float du = fmaf(e, e, fmaf(bq, bq, a2q));
@@ -531,14 +652,40 @@ __device__ __forceinline__ void process_tile(TileState<QR, QC>& S, const FrameDe
         }
     }
 
-    // ---- final merge per query; neighbour outputs
+    // ---- final selection; neighbour outputs
 #pragma unroll
     for (int q = 0; q < Q; ++q)
         if (L == 0) S.cnt[q] = cnt[q];
     wave_sync();
+    // queries whose buffer overflowed during the scan already hold a sorted
+    // list: merge their last candidates one query at a time (rare)
     for (int q = 0; q < Q; ++q) {
         const int qr = q / QC, qc = q % QC;
-        if (qr < nqr && qc < nqc) flush_query(S, f, r0, c0, q, uni(S.cnt[q]), true);
+        if (qr < nqr && qc < nqc && uni(S.listn[q]) > 0)
+            flush_query(S, f, r0, c0, q, uni(S.cnt[q]), true);
+    }
+    wave_sync();
+    {
+        // all other queries: one segmented sort of their candidate buffers
+        const int cq = S.cnt[sq];
+        const bool own = sok && S.listn[sq] == 0;
+        uint64_t x[E];
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            const int e = lp * E + u;
+            x[u] = (own && e < cq) ? S.pend[sq][e] : KEY_INF;
+        }
+        seg_sort_key<E>(x, lp);
+        const size_t pix = (size_t)(r0 + sqr) * W + c0 + sqc;
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            const int e = lp * E + u;
+            if (own && e < K) {
+                S.list[sq][e] = (uint32_t)x[u];
+                if (f.out_nbr) f.out_nbr[pix * K + e] = (int32_t)(uint32_t)x[u];
+                if (f.out_dist) f.out_dist[pix * K + e] = __uint_as_float((uint32_t)(x[u] >> 32));
+            }
+        }
     }
     wave_sync();
 
@@ -550,15 +697,15 @@ __device__ __forceinline__ void process_tile(TileState<QR, QC>& S, const FrameDe
         const int qr = q / QC, qc = q % QC;
         if (qr >= nqr || qc >= nqc) continue;
         float s = 0.0f;
-        for (int k0 = 0; k0 < K; k0 += 8) {
-            float v[8];
+        for (int k0 = 0; k0 < K; k0 += 16) {
+            float v[16];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < 16; ++u) {
                 const uint32_t idx = (k0 + u < K) ? S.list[q][k0 + u] : 0xffffffffu;
                 v[u] = idx < (uint32_t)npx ? prob[(size_t)idx * C + cl] : 0.0f;
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
+            for (int u = 0; u < 16; ++u)
                 if (k0 + u < K) s = s + v[u];
         }
         S.sums[q][cl] = s;
