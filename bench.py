@@ -45,6 +45,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--legs", default="plain,batch,serve",
+                    help="comma list of: plain (headline), batch (uneven / small-frame "
+                         "batches), serve (Poisson mixed stream)")
+    ap.add_argument("--serve-frames", type=int, default=2000)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
     return ap.parse_args()
 
 
@@ -67,6 +72,85 @@ def cpu_baseline(spec, pc1, prob, target_s):
     return {"value": n / dt, "unit": "pixels/s", "cores": nt, "kind": "oracle",
             "sample": f"{n} random pixels of the W480xH380 brain-like frame (K=40, +-14 rows), "
                       f"{dt:.1f} s on {nt} threads"}
+
+
+def time_gpu(fn, reps):
+    import torch
+
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def batch_leg(ctx, plan, stream, reps=3):
+    """Uneven and small-frame batches: one fused launch vs one launch per frame."""
+    from paper_2404_10631_amd import _lib, inputs
+    from paper_2404_10631_amd.frames import DeviceFrame
+
+    out = {}
+    for wl in (inputs.config2(), inputs.config3()):
+        frames = [DeviceFrame(*f.make(), f.K, f.R, f.lam, with_nbr=False) for f in wl.frames]
+        cfs = [f.as_c() for f in frames]
+        t_batch = time_gpu(lambda: _lib.knnf_filter_batch(ctx, cfs, plan, stream), reps)
+
+        def plain():
+            for c in cfs:
+                _lib.knnf_filter(ctx, c, plan, stream)
+
+        t_plain = time_gpu(plain, reps)
+        px = wl.pixels
+        out[wl.name] = {"frames": len(frames), "pixels": px,
+                        "batched_pixels_per_s": round(px / t_batch, 1),
+                        "plain_pixels_per_s": round(px / t_plain, 1),
+                        "batched_ms": round(t_batch * 1e3, 4), "plain_ms": round(t_plain * 1e3, 4),
+                        "speedup": round(t_plain / t_batch, 3)}
+        del frames
+    return out
+
+
+def serve_leg(ctx, plan, n_frames, rate):
+    """Poisson stream of mixed frame sizes: continuous-batching server vs plain
+    one-frame-at-a-time launches, both fed by the same arrival schedule."""
+    from paper_2404_10631_amd import _lib, inputs
+    from paper_2404_10631_amd.serve import HostFrame, Server, replay, summarize
+
+    stream = inputs.serve_stream(n=n_frames, rate_hz=rate)
+    # a pool of distinct frames per class, reused round-robin (same shapes and
+    # statistics as drawing every frame afresh)
+    distinct = {"S": 32, "M": 16, "L": 6}
+    pool = {}
+    for cls, spec_kw in inputs.SERVE_CLASSES.items():
+        pool[cls] = []
+        for k in range(distinct[cls]):
+            fs = inputs.FrameSpec(spec_kw["gen"], spec_kw["H"], spec_kw["W"], 10000 + 97 * k,
+                                  K=spec_kw["K"], R=spec_kw["R"])
+            pool[cls].append(HostFrame(*fs.make(), fs.K, fs.R, fs.lam, cls=cls))
+    count = {c: 0 for c in pool}
+    frames, arrivals = [], []
+    for t, cls, _ in stream:
+        frames.append(pool[cls][count[cls] % len(pool[cls])])
+        count[cls] += 1
+        arrivals.append(t)
+    warm = min(100, n_frames // 10)
+    pool_bytes = 2 << 30
+    res = {}
+    for name, mode in (("served", _lib.KNNF_SERVE_BATCHED), ("plain", _lib.KNNF_SERVE_PLAIN)):
+        with Server(ctx, pool_bytes, mode=mode, plan=plan) as srv:
+            r = replay(srv, frames, arrivals, warmup=warm, timeout_s=300)
+            res[name] = summarize(frames, r, classes=list(pool))
+            # saturation: the same frames all at once
+            nb = min(len(frames), 400)
+            r2 = replay(srv, frames[:nb], [0.0] * nb, timeout_s=300)
+            res[name]["saturated_pixels_per_s"] = summarize(frames[:nb], r2)["pixels_per_s"]
+    mix = {c: count[c] for c in count}
+    res["stream"] = {"frames": n_frames, "rate_hz": rate, "mix": mix, "warmup_frames": warm,
+                     "offered_pixels_per_s": round(sum(f.pixels for f in frames) /
+                                                   max(arrivals[-1], 1e-9), 1)}
+    return res
 
 
 def main():
@@ -121,13 +205,39 @@ def main():
     px = spec.pixels
     value = px * args.steps / wall
 
-    pairs = spec.pairs()
-    achieved = pairs * FLOP_PER_PAIR / (kernel_ms * 1e-3) / 1e12
+    # Work actually done by one launch: candidate distances evaluated, counted
+    # by the kernel itself in one extra (untimed) launch.
+    _lib.knnf_stats_enable(ctx, True)
+    _lib.knnf_stats_read(ctx, reset=True)
+    _lib.knnf_filter(ctx, cf, plan, stream)
+    evaluated, _ = _lib.knnf_stats_read(ctx, reset=True)
+    _lib.knnf_stats_enable(ctx, False)
+    window_pairs = spec.pairs()
+    achieved = evaluated * FLOP_PER_PAIR / (kernel_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
                 "traffic": None,
                 "kernel": "filter_frame_kernel", "kernel_ms": round(kernel_ms, 5),
-                "work": f"{pairs} window pairs x {FLOP_PER_PAIR} FLOP"}
+                "work": f"{evaluated} evaluated pairs x {FLOP_PER_PAIR} FLOP",
+                "window_pairs": window_pairs,
+                "window_equivalent_tflops": round(window_pairs * FLOP_PER_PAIR /
+                                                  (kernel_ms * 1e-3) / 1e12, 3)}
+    # the exhaustive search on the same frame (every window pair evaluated)
+    exh = dict(plan, search=0)
+    for _ in range(2):
+        _lib.knnf_filter(ctx, cf, exh, stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        _lib.knnf_filter(ctx, cf, exh, stream)
+    e1.record()
+    torch.cuda.synchronize()
+    exh_ms = e0.elapsed_time(e1) / 10
+    exh_tflops = (window_pairs + 64 * px) * FLOP_PER_PAIR / (exh_ms * 1e-3) / 1e12
+    exhaustive = {"kernel_ms": round(exh_ms, 5), "pixels_per_s": round(px / (exh_ms * 1e-3), 1),
+                  "achieved_tflops": round(exh_tflops, 3),
+                  "frac": round(exh_tflops / PEAK_FP32_VECTOR_TFLOPS, 4)}
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "pixels/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 5),
@@ -139,8 +249,17 @@ def main():
         "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 5),
                        "p99": round(float(np.percentile(lat_ms, 99)), 5)},
         "roofline": roofline,
+        "exhaustive_search": exhaustive,
     }
+    legs = set(args.legs.split(","))
+    if "batch" in legs:
+        print("bench: batch leg", file=sys.stderr, flush=True)
+        out["batched"] = batch_leg(ctx, plan, stream)
+    if "serve" in legs:
+        print("bench: serve leg", file=sys.stderr, flush=True)
+        out["serving"] = serve_leg(ctx, plan, args.serve_frames, args.serve_rate)
     if not args.no_cpu:
+        print("bench: cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(spec, pc1, prob, args.cpu_seconds)
     _lib.knnf_destroy(ctx)
     print(json.dumps(out), flush=True)

@@ -171,10 +171,106 @@ knnf_status knnf_tune(knnf_ctx* ctx, const knnf_frame* frames, int n, int reps,
                       void* stream, knnf_plan* best);
 
 /*
+ * Work counters of the filtering kernels, for roofline accounting.  While
+ * enabled, every launch adds the number of candidate distances it evaluated
+ * for on-frame query pixels (pass-A block slots included) and the number of
+ * tiles it processed.  Off by default; enabling allocates 16 bytes of device
+ * memory once.  knnf_stats_read synchronises the device; reset != 0 zeroes
+ * the counters after reading.
+ */
+knnf_status knnf_stats_enable(knnf_ctx* ctx, int on);
+knnf_status knnf_stats_read(knnf_ctx* ctx, uint64_t* pairs, uint64_t* tiles, int reset);
+
+/*
  * Bytes of device memory a frame occupies (inputs + outputs, each buffer
  * rounded up to 256 bytes), used to admit frames into a fixed pool.
  */
 size_t knnf_frame_bytes(int H, int W, int C, int K, int with_nbr);
+
+/* ---------------------------------------------------------------------------
+ * Serving.  The paper's real-time requirement is per frame: a frame must be
+ * classified before the sensor delivers the next one (Sec. I; Sec. II.B for
+ * the neurosurgical and dermatological use cases).  A server accepts frames
+ * of different sizes from the host at any time, admits them by device memory
+ * into a caller-owned pool, keeps inputs and outputs resident, and processes
+ * all admitted frames together (continuous batching): every GPU step is one
+ * batched launch over tile ranges of all admitted frames, bounded by a tile
+ * budget, so a large frame is processed in slices and frames that arrive
+ * meanwhile join the next step.  Up to `max_inflight` steps are queued on
+ * separate streams, so the next step is ready when the current one ends.
+ *
+ * KNNF_SERVE_PLAIN is the comparison baseline: one whole frame per launch,
+ * one launch at a time, in arrival order.
+ *
+ * Outputs are bitwise identical to knnf_filter() of the same frame alone.
+ * The server and ticket functions may be called from any host thread.
+ * ------------------------------------------------------------------------- */
+typedef struct knnf_server knnf_server;
+
+typedef enum { KNNF_SERVE_BATCHED = 0, KNNF_SERVE_PLAIN = 1 } knnf_serve_mode;
+
+typedef struct {
+    int32_t mode;          /* knnf_serve_mode                                   */
+    int32_t max_queue;     /* frames submitted but not admitted; 0: 4096         */
+    int32_t max_inflight;  /* GPU steps queued at once (batched mode), 0: 2; <=4 */
+    int32_t step_tiles;    /* tile budget of one batched step; 0: 32768          */
+    knnf_plan plan;        /* kernel plan; zero fields: the context's default    */
+} knnf_server_opts;
+
+typedef struct {
+    int32_t H, W, C, K, R;  /* as in knnf_frame                                  */
+    float lambda;
+    const float* pc1;       /* host memory, H*W; must stay valid until the frame */
+    const float* prob;      /* is done (pinned memory allows asynchronous copies) */
+    int32_t with_nbr;       /* keep out_nbr and out_dist as well                 */
+    double t_arrival;       /* arrival time on knnf_server_clock(); < 0: now     */
+} knnf_host_frame;
+
+typedef struct {
+    int32_t done;           /* 1 once the outputs are final in device memory     */
+    int32_t released;
+    double t_arrival;       /* knnf_server_clock() seconds                       */
+    double t_admit;         /* pool memory granted, copy to the device enqueued  */
+    double t_launch;        /* first GPU step containing the frame enqueued      */
+    double t_done;          /* completion observed by the server                 */
+} knnf_ticket_info;
+
+/* Monotonic clock of the server, in seconds. */
+double knnf_server_clock(void);
+
+/*
+ * Create a server on `ctx` that sub-allocates frames from the device buffer
+ * `pool` (pool_bytes bytes, caller-owned, must outlive the server).  Starts
+ * one scheduler thread.  opts may be NULL (batched mode, defaults).
+ */
+knnf_status knnf_server_create(knnf_server** out, knnf_ctx* ctx, void* pool,
+                               size_t pool_bytes, const knnf_server_opts* opts);
+
+/*
+ * Submit a frame.  Returns a ticket.  KNNF_EINVAL for a bad frame,
+ * KNNF_ENOMEM if the frame can never fit the pool, KNNF_EAGAIN if the
+ * admission queue is full (retry later).
+ */
+knnf_status knnf_server_submit(knnf_server* srv, const knnf_host_frame* frame,
+                               uint64_t* ticket);
+
+/* State and timestamps of a ticket.  KNNF_EINVAL for an unknown ticket. */
+knnf_status knnf_server_poll(knnf_server* srv, uint64_t ticket, knnf_ticket_info* info);
+
+/*
+ * Device view of a finished frame: pointers into the pool (inputs and
+ * outputs), valid until knnf_server_release().  KNNF_ESTATE if not done.
+ */
+knnf_status knnf_server_result(knnf_server* srv, uint64_t ticket, knnf_frame* view);
+
+/* Return a finished frame's pool memory.  KNNF_ESTATE if not done. */
+knnf_status knnf_server_release(knnf_server* srv, uint64_t ticket);
+
+/* Wait until every submitted frame is done (timeout in seconds; <= 0: none). */
+knnf_status knnf_server_drain(knnf_server* srv, double timeout_s);
+
+/* Stop the scheduler after the GPU work in flight ends, and free the server. */
+knnf_status knnf_server_destroy(knnf_server* srv);
 
 /* Text of the last error on the calling thread ("" if none). */
 const char* knnf_last_error(void);

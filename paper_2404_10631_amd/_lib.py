@@ -53,6 +53,31 @@ class knnf_plan(ctypes.Structure):
                 "tile_cols": self.tile_cols, "waves": self.waves}
 
 
+KNNF_SERVE_BATCHED = 0
+KNNF_SERVE_PLAIN = 1
+
+
+class knnf_server_opts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("max_queue", ctypes.c_int32),
+                ("max_inflight", ctypes.c_int32), ("step_tiles", ctypes.c_int32),
+                ("plan", knnf_plan)]
+
+
+class knnf_host_frame(ctypes.Structure):
+    _fields_ = [
+        ("H", ctypes.c_int32), ("W", ctypes.c_int32), ("C", ctypes.c_int32),
+        ("K", ctypes.c_int32), ("R", ctypes.c_int32), ("lam", ctypes.c_float),
+        ("pc1", ctypes.c_void_p), ("prob", ctypes.c_void_p),
+        ("with_nbr", ctypes.c_int32), ("t_arrival", ctypes.c_double),
+    ]
+
+
+class knnf_ticket_info(ctypes.Structure):
+    _fields_ = [("done", ctypes.c_int32), ("released", ctypes.c_int32),
+                ("t_arrival", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_launch", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
 class KnnfError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
@@ -72,7 +97,18 @@ _SIGS = {
     "knnf_filter_batch": (_I, [_P, ctypes.POINTER(knnf_frame), _I, ctypes.POINTER(knnf_plan), _P]),
     "knnf_tune": (_I, [_P, ctypes.POINTER(knnf_frame), _I, _I, _P, ctypes.POINTER(knnf_plan)]),
     "knnf_frame_bytes": (ctypes.c_size_t, [_I, _I, _I, _I, _I]),
+    "knnf_stats_enable": (_I, [_P, _I]),
+    "knnf_stats_read": (_I, [_P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64), _I]),
     "knnf_last_error": (ctypes.c_char_p, []),
+    "knnf_server_clock": (ctypes.c_double, []),
+    "knnf_server_create": (_I, [ctypes.POINTER(_P), _P, _P, ctypes.c_size_t,
+                                ctypes.POINTER(knnf_server_opts)]),
+    "knnf_server_submit": (_I, [_P, ctypes.POINTER(knnf_host_frame), ctypes.POINTER(ctypes.c_uint64)]),
+    "knnf_server_poll": (_I, [_P, ctypes.c_uint64, ctypes.POINTER(knnf_ticket_info)]),
+    "knnf_server_result": (_I, [_P, ctypes.c_uint64, ctypes.POINTER(knnf_frame)]),
+    "knnf_server_release": (_I, [_P, ctypes.c_uint64]),
+    "knnf_server_drain": (_I, [_P, ctypes.c_double]),
+    "knnf_server_destroy": (_I, [_P]),
     "knnf_version": (ctypes.c_char_p, []),
 }
 
@@ -166,5 +202,59 @@ def knnf_tune(ctx: int, frames, reps: int = 3, stream: int = 0) -> knnf_plan:
     return best
 
 
+def knnf_stats_enable(ctx: int, on: bool) -> None:
+    check(load().knnf_stats_enable(ctx, 1 if on else 0))
+
+
+def knnf_stats_read(ctx: int, reset: bool = True) -> tuple[int, int]:
+    p, t = ctypes.c_uint64(), ctypes.c_uint64()
+    check(load().knnf_stats_read(ctx, ctypes.byref(p), ctypes.byref(t), 1 if reset else 0))
+    return p.value, t.value
+
+
 def knnf_frame_bytes(H: int, W: int, C: int, K: int, with_nbr: bool) -> int:
     return int(load().knnf_frame_bytes(H, W, C, K, 1 if with_nbr else 0))
+
+
+def knnf_server_clock() -> float:
+    return float(load().knnf_server_clock())
+
+
+def knnf_server_create(ctx: int, pool_ptr: int, pool_bytes: int, opts: knnf_server_opts | None = None) -> int:
+    h = ctypes.c_void_p()
+    check(load().knnf_server_create(ctypes.byref(h), ctx, pool_ptr, pool_bytes,
+                                    ctypes.byref(opts) if opts is not None else None))
+    return h.value
+
+
+def knnf_server_submit(srv: int, frame: knnf_host_frame) -> tuple[int, int]:
+    """Returns (status, ticket); KNNF_EAGAIN is returned, not raised."""
+    t = ctypes.c_uint64()
+    st = load().knnf_server_submit(srv, ctypes.byref(frame), ctypes.byref(t))
+    if st not in (KNNF_OK, KNNF_EAGAIN):
+        check(st)
+    return st, t.value
+
+
+def knnf_server_poll(srv: int, ticket: int) -> knnf_ticket_info:
+    info = knnf_ticket_info()
+    check(load().knnf_server_poll(srv, ticket, ctypes.byref(info)))
+    return info
+
+
+def knnf_server_result(srv: int, ticket: int) -> knnf_frame:
+    v = knnf_frame()
+    check(load().knnf_server_result(srv, ticket, ctypes.byref(v)))
+    return v
+
+
+def knnf_server_release(srv: int, ticket: int) -> None:
+    check(load().knnf_server_release(srv, ticket))
+
+
+def knnf_server_drain(srv: int, timeout_s: float = 0.0) -> None:
+    check(load().knnf_server_drain(srv, float(timeout_s)))
+
+
+def knnf_server_destroy(srv: int) -> None:
+    check(load().knnf_server_destroy(srv))

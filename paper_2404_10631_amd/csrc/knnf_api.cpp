@@ -16,22 +16,24 @@
 
 #include "../../include/knnf.h"
 #include "knnf_device.h"
-
-namespace knnf {
-int launch_zero_counter(uint32_t* d_counter, void* stream);
-}
+#include "knnf_internal.h"
 
 namespace {
 
 thread_local std::string g_err;
 
-knnf_status fail(knnf_status st, const char* fmt, ...) {
+knnf_status vfail(knnf_status st, const char* fmt, va_list ap) {
     char buf[512];
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    g_err = buf;
+    return st;
+}
+
+knnf_status fail(knnf_status st, const char* fmt, ...) {
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vfail(st, fmt, ap);
     va_end(ap);
-    g_err = buf;
     return st;
 }
 
@@ -39,24 +41,23 @@ knnf_status hip_fail(hipError_t e, const char* what) {
     return fail(KNNF_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-// One slot of batch tables: device frame table + task prefix + claim counter,
-// and a pinned host staging copy.  `done` is recorded after the launch that
-// uses the slot, so the slot is reused only after that launch has finished.
+// One slot of batch tables: device work table (frame descriptors, task
+// prefix, first tiles, claim counter) and a pinned host staging copy.  `done`
+// is recorded after the launch that uses the slot, so the slot is reused only
+// after that launch has finished.
 struct BatchSlot {
-    void* dev = nullptr;      // [FrameDesc x cap][uint32 x (cap+1)][uint32 counter]
-    void* host = nullptr;     // pinned staging of the same layout
-    size_t cap = 0;           // frames
+    void* dev = nullptr;
+    void* host = nullptr;
+    size_t cap = 0;           // work items
     hipEvent_t done = nullptr;
     bool recorded = false;
 };
 
-size_t slot_bytes(size_t cap) {
-    size_t a = cap * sizeof(knnf::FrameDesc);
-    a = (a + 255) & ~size_t(255);
-    size_t b = (cap + 1) * sizeof(uint32_t);
-    b = (b + 255) & ~size_t(255);
-    return a + b + 256;
-}
+size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
+size_t off_task_start(size_t cap) { return round256(cap * sizeof(knnf::FrameDesc)); }
+size_t off_tile_base(size_t cap) { return off_task_start(cap) + round256((cap + 1) * sizeof(uint32_t)); }
+size_t off_counter(size_t cap) { return off_tile_base(cap) + round256(cap * sizeof(uint32_t)); }
+size_t slot_bytes(size_t cap) { return off_counter(cap) + 256; }
 
 constexpr int kSlots = 4;
 
@@ -69,6 +70,8 @@ struct knnf_ctx {
     std::mutex mu;
     BatchSlot slots[kSlots];
     int next_slot = 0;
+    unsigned long long* d_stats = nullptr;  // work counters while enabled
+    bool stats_on = false;
 };
 
 namespace {
@@ -84,7 +87,7 @@ knnf_plan default_plan() {
 
 const int kShapes[][2] = {{1, 8}, {1, 16}, {2, 4}, {2, 8}, {4, 4}};
 
-bool plan_ok(const knnf_plan& p) {
+bool plan_ok_impl(const knnf_plan& p) {
     if (p.search != KNNF_SEARCH_EXHAUSTIVE && p.search != KNNF_SEARCH_PRUNED) return false;
     bool shape = false;
     for (const auto& s : kShapes) shape |= (p.tile_rows == s[0] && p.tile_cols == s[1]);
@@ -93,7 +96,7 @@ bool plan_ok(const knnf_plan& p) {
     return true;
 }
 
-knnf_plan resolve(const knnf_ctx* ctx, const knnf_plan* p) {
+knnf_plan resolve_impl(const knnf_ctx* ctx, const knnf_plan* p) {
     knnf_plan r = ctx->plan;
     if (p) {
         r.search = p->search;
@@ -113,7 +116,7 @@ knnf::LaunchCfg to_cfg(const knnf_plan& p) {
     return c;
 }
 
-knnf::FrameDesc to_desc(const knnf_frame& f) {
+knnf::FrameDesc to_desc_impl(const knnf_frame& f) {
     knnf::FrameDesc d;
     d.pc1 = f.pc1;
     d.prob = f.prob;
@@ -127,10 +130,11 @@ knnf::FrameDesc to_desc(const knnf_frame& f) {
     d.K = f.K;
     d.R = f.R;
     d.lambda = f.lambda;
+    d.stats = nullptr;
     return d;
 }
 
-knnf_status validate(const knnf_frame* f, int index) {
+knnf_status validate_impl(const knnf_frame* f, int index) {
     if (!f) return fail(KNNF_EINVAL, "frame %d: NULL frame", index);
     if (f->H < 1 || f->W < 1)
         return fail(KNNF_EINVAL, "frame %d: H=%d W=%d must be >= 1", index, f->H, f->W);
@@ -164,13 +168,110 @@ double task_cost(const knnf_frame& f, int Q) {
 
 }  // namespace
 
+namespace knnf {
+
+knnf_status set_error(knnf_status st, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vfail(st, fmt, ap);
+    va_end(ap);
+    return st;
+}
+knnf_status validate_frame(const knnf_frame* f, int index) { return validate_impl(f, index); }
+knnf_plan resolve_plan(const knnf_ctx* ctx, const knnf_plan* p) { return resolve_impl(ctx, p); }
+bool plan_valid(const knnf_plan& p) { return plan_ok_impl(p); }
+FrameDesc desc_of(const knnf_frame& f) { return to_desc_impl(f); }
+uint32_t tiles_of(int H, int W, const knnf_plan& p) {
+    return (uint32_t)((H + p.tile_rows - 1) / p.tile_rows) * (uint32_t)((W + p.tile_cols - 1) / p.tile_cols);
+}
+int ctx_device(const knnf_ctx* ctx) { return ctx->device; }
+
+knnf_status launch_items(knnf_ctx* ctx, const WorkItem* items, int n, const knnf_plan& p,
+                         void* stream) {
+    uint64_t total = 0;
+    for (int k = 0; k < n; ++k) {
+        total += items[k].ntiles;
+        if (total > 0xfff00000ull) return fail(KNNF_EINVAL, "batched launch: too much work");
+    }
+    if (total == 0) return KNNF_OK;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    int prev = 0;
+    hipGetDevice(&prev);
+    if (prev != ctx->device) hipSetDevice(ctx->device);
+    struct Restore {
+        int prev, dev;
+        ~Restore() { if (prev != dev) hipSetDevice(prev); }
+    } restore{prev, ctx->device};
+
+    BatchSlot& s = ctx->slots[ctx->next_slot];
+    ctx->next_slot = (ctx->next_slot + 1) % kSlots;
+    hipError_t e;
+    if (s.recorded) {
+        e = hipEventSynchronize(s.done);
+        if (e != hipSuccess) return hip_fail(e, "batch slot wait");
+        s.recorded = false;
+    }
+    if (s.cap < (size_t)n) {
+        size_t cap = std::max<size_t>(64, s.cap);
+        while (cap < (size_t)n) cap *= 2;
+        if (s.dev) hipFree(s.dev);
+        if (s.host) hipHostFree(s.host);
+        s.dev = s.host = nullptr;
+        s.cap = 0;
+        e = hipMalloc(&s.dev, slot_bytes(cap));
+        if (e != hipSuccess) return fail(KNNF_ENOMEM, "batch table: %s", hipGetErrorString(e));
+        e = hipHostMalloc(&s.host, slot_bytes(cap), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            hipFree(s.dev);
+            s.dev = nullptr;
+            return fail(KNNF_ENOMEM, "batch staging: %s", hipGetErrorString(e));
+        }
+        s.cap = cap;
+    }
+    knnf::FrameDesc* hf = (knnf::FrameDesc*)s.host;
+    uint32_t* hts = (uint32_t*)((char*)s.host + off_task_start(s.cap));
+    uint32_t* htb = (uint32_t*)((char*)s.host + off_tile_base(s.cap));
+    uint32_t acc = 0;
+    for (int k = 0; k < n; ++k) {
+        hf[k] = items[k].f;
+        hf[k].stats = ctx->stats_on ? ctx->d_stats : nullptr;
+        hts[k] = acc;
+        htb[k] = items[k].tile0;
+        acc += items[k].ntiles;
+    }
+    hts[n] = acc;
+    hipStream_t hs = (hipStream_t)stream;
+    // one copy of the whole table prefix: descriptors, prefix, first tiles
+    e = hipMemcpyAsync(s.dev, s.host, off_counter(s.cap), hipMemcpyHostToDevice, hs);
+    if (e != hipSuccess) return hip_fail(e, "batch table copy");
+    uint32_t* d_ctr = (uint32_t*)((char*)s.dev + off_counter(s.cap));
+    int rc = knnf::launch_zero_counter(d_ctr, stream);
+    if (rc != 0) return hip_fail((hipError_t)rc, "counter reset");
+    const knnf::LaunchCfg cfg = to_cfg(p);
+    const uint64_t need_blocks = (total + p.waves - 1) / p.waves;
+    const int per_cu = knnf::persistent_blocks_per_cu(cfg);
+    const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(need_blocks,
+                                                  (uint64_t)ctx->num_cu * per_cu));
+    rc = knnf::launch_filter_batch((const knnf::FrameDesc*)s.dev,
+                                   (const uint32_t*)((char*)s.dev + off_task_start(s.cap)),
+                                   (const uint32_t*)((char*)s.dev + off_tile_base(s.cap)),
+                                   (uint32_t)n, (uint32_t)total, d_ctr, cfg, (int)grid, stream);
+    if (rc != 0) return hip_fail((hipError_t)rc, "batched launch");
+    e = hipEventRecord(s.done, hs);
+    if (e != hipSuccess) return hip_fail(e, "batch slot record");
+    s.recorded = true;
+    return KNNF_OK;
+}
+
+}  // namespace knnf
+
 extern "C" {
 
 const char* knnf_last_error(void) { return g_err.c_str(); }
 
 const char* knnf_version(void) { return "knnf 0.1.0 gfx950"; }
 
-knnf_status knnf_validate(const knnf_frame* frame) { return validate(frame, 0); }
+knnf_status knnf_validate(const knnf_frame* frame) { return validate_impl(frame, 0); }
 
 size_t knnf_frame_bytes(int H, int W, int C, int K, int with_nbr) {
     if (H < 1 || W < 1 || C < 1 || K < 1) return 0;
@@ -224,6 +325,7 @@ knnf_status knnf_destroy(knnf_ctx* ctx) {
         if (s.dev) hipFree(s.dev);
         if (s.host) hipHostFree(s.host);
     }
+    if (ctx->d_stats) hipFree(ctx->d_stats);
     hipSetDevice(prev);
     delete ctx;
     return KNNF_OK;
@@ -231,8 +333,8 @@ knnf_status knnf_destroy(knnf_ctx* ctx) {
 
 knnf_status knnf_set_default_plan(knnf_ctx* ctx, const knnf_plan* plan) {
     if (!ctx || !plan) return fail(KNNF_EINVAL, "knnf_set_default_plan: NULL argument");
-    knnf_plan p = resolve(ctx, plan);
-    if (!plan_ok(p)) return fail(KNNF_EINVAL, "invalid plan");
+    knnf_plan p = resolve_impl(ctx, plan);
+    if (!plan_ok_impl(p)) return fail(KNNF_EINVAL, "invalid plan");
     ctx->plan = p;
     return KNNF_OK;
 }
@@ -246,14 +348,16 @@ knnf_status knnf_get_default_plan(const knnf_ctx* ctx, knnf_plan* plan) {
 knnf_status knnf_filter(knnf_ctx* ctx, const knnf_frame* frame, const knnf_plan* plan,
                         void* stream) {
     if (!ctx) return fail(KNNF_EINVAL, "knnf_filter: NULL context");
-    knnf_status st = validate(frame, 0);
+    knnf_status st = validate_impl(frame, 0);
     if (st != KNNF_OK) return st;
-    const knnf_plan p = resolve(ctx, plan);
-    if (!plan_ok(p)) return fail(KNNF_EINVAL, "knnf_filter: invalid plan");
+    const knnf_plan p = resolve_impl(ctx, plan);
+    if (!plan_ok_impl(p)) return fail(KNNF_EINVAL, "knnf_filter: invalid plan");
     int prev = 0;
     hipGetDevice(&prev);
     if (prev != ctx->device) hipSetDevice(ctx->device);
-    const int e = knnf::launch_filter_frame(to_desc(*frame), to_cfg(p), stream);
+    knnf::FrameDesc desc = to_desc_impl(*frame);
+    desc.stats = ctx->stats_on ? ctx->d_stats : nullptr;
+    const int e = knnf::launch_filter_frame(desc, to_cfg(p), stream);
     if (prev != ctx->device) hipSetDevice(prev);
     if (e != 0) return hip_fail((hipError_t)e, "knnf_filter launch");
     return KNNF_OK;
@@ -265,92 +369,58 @@ knnf_status knnf_filter_batch(knnf_ctx* ctx, const knnf_frame* frames, int n,
     if (n < 0 || (n > 0 && !frames)) return fail(KNNF_EINVAL, "knnf_filter_batch: bad frame list");
     if (n == 0) return KNNF_OK;
     for (int i = 0; i < n; ++i) {
-        knnf_status st = validate(&frames[i], i);
+        knnf_status st = validate_impl(&frames[i], i);
         if (st != KNNF_OK) return st;
     }
-    const knnf_plan p = resolve(ctx, plan);
-    if (!plan_ok(p)) return fail(KNNF_EINVAL, "knnf_filter_batch: invalid plan");
-    const int QR = p.tile_rows, QC = p.tile_cols;
-    const int Q = QR * QC;
-
-    // Largest strip cost first: long tasks start early, short ones fill the tail.
+    const knnf_plan p = resolve_impl(ctx, plan);
+    if (!plan_ok_impl(p)) return fail(KNNF_EINVAL, "knnf_filter_batch: invalid plan");
+    const int Q = p.tile_rows * p.tile_cols;
+    // Largest tile cost first: long tasks start early, short ones fill the tail.
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         return task_cost(frames[a], Q) > task_cost(frames[b], Q);
     });
-    uint64_t total = 0;
-    std::vector<uint32_t> start(n + 1);
+    std::vector<knnf::WorkItem> items(n);
     for (int k = 0; k < n; ++k) {
         const knnf_frame& f = frames[order[k]];
-        start[k] = (uint32_t)total;
-        total += (uint64_t)((f.H + QR - 1) / QR) * (uint64_t)((f.W + QC - 1) / QC);
-        if (total > 0xfff00000ull) return fail(KNNF_EINVAL, "knnf_filter_batch: too much work");
+        items[k].f = to_desc_impl(f);
+        items[k].tile0 = 0;
+        items[k].ntiles = knnf::tiles_of(f.H, f.W, p);
     }
-    start[n] = (uint32_t)total;
+    return knnf::launch_items(ctx, items.data(), n, p, stream);
+}
 
-    std::lock_guard<std::mutex> lock(ctx->mu);
+knnf_status knnf_stats_enable(knnf_ctx* ctx, int on) {
+    if (!ctx) return fail(KNNF_EINVAL, "knnf_stats_enable: NULL context");
+    if (on && !ctx->d_stats) {
+        int prev = 0;
+        hipGetDevice(&prev);
+        hipSetDevice(ctx->device);
+        hipError_t e = hipMalloc((void**)&ctx->d_stats, 2 * sizeof(unsigned long long));
+        if (e == hipSuccess) e = hipMemset(ctx->d_stats, 0, 2 * sizeof(unsigned long long));
+        hipSetDevice(prev);
+        if (e != hipSuccess) return fail(KNNF_ENOMEM, "knnf_stats_enable: %s", hipGetErrorString(e));
+    }
+    ctx->stats_on = on != 0;
+    return KNNF_OK;
+}
+
+knnf_status knnf_stats_read(knnf_ctx* ctx, uint64_t* pairs, uint64_t* tiles, int reset) {
+    if (!ctx || !pairs || !tiles) return fail(KNNF_EINVAL, "knnf_stats_read: NULL argument");
+    *pairs = *tiles = 0;
+    if (!ctx->d_stats) return KNNF_OK;
     int prev = 0;
     hipGetDevice(&prev);
-    if (prev != ctx->device) hipSetDevice(ctx->device);
-    struct Restore {
-        int prev, dev;
-        ~Restore() { if (prev != dev) hipSetDevice(prev); }
-    } restore{prev, ctx->device};
-
-    BatchSlot& s = ctx->slots[ctx->next_slot];
-    ctx->next_slot = (ctx->next_slot + 1) % kSlots;
-    hipError_t e;
-    if (s.recorded) {
-        e = hipEventSynchronize(s.done);
-        if (e != hipSuccess) return hip_fail(e, "batch slot wait");
-        s.recorded = false;
-    }
-    if (s.cap < (size_t)n) {
-        size_t cap = std::max<size_t>(64, s.cap);
-        while (cap < (size_t)n) cap *= 2;
-        if (s.dev) hipFree(s.dev);
-        if (s.host) hipHostFree(s.host);
-        s.dev = s.host = nullptr;
-        s.cap = 0;
-        e = hipMalloc(&s.dev, slot_bytes(cap));
-        if (e != hipSuccess) return fail(KNNF_ENOMEM, "batch table: %s", hipGetErrorString(e));
-        e = hipHostMalloc(&s.host, slot_bytes(cap), hipHostMallocDefault);
-        if (e != hipSuccess) {
-            hipFree(s.dev);
-            s.dev = nullptr;
-            return fail(KNNF_ENOMEM, "batch staging: %s", hipGetErrorString(e));
-        }
-        s.cap = cap;
-    }
-    size_t off_ts = (s.cap * sizeof(knnf::FrameDesc) + 255) & ~size_t(255);
-    size_t off_ctr = off_ts + (((s.cap + 1) * sizeof(uint32_t) + 255) & ~size_t(255));
-    knnf::FrameDesc* hf = (knnf::FrameDesc*)s.host;
-    uint32_t* hts = (uint32_t*)((char*)s.host + off_ts);
-    for (int k = 0; k < n; ++k) hf[k] = to_desc(frames[order[k]]);
-    memcpy(hts, start.data(), (n + 1) * sizeof(uint32_t));
-    hipStream_t hs = (hipStream_t)stream;
-    e = hipMemcpyAsync(s.dev, s.host, n * sizeof(knnf::FrameDesc), hipMemcpyHostToDevice, hs);
-    if (e != hipSuccess) return hip_fail(e, "batch table copy");
-    e = hipMemcpyAsync((char*)s.dev + off_ts, hts, (n + 1) * sizeof(uint32_t),
-                       hipMemcpyHostToDevice, hs);
-    if (e != hipSuccess) return hip_fail(e, "batch prefix copy");
-    uint32_t* d_ctr = (uint32_t*)((char*)s.dev + off_ctr);
-    int rc = knnf::launch_zero_counter(d_ctr, stream);
-    if (rc != 0) return hip_fail((hipError_t)rc, "counter reset");
-    const knnf::LaunchCfg cfg = to_cfg(p);
-    const uint64_t wave_tasks = total;
-    const uint64_t need_blocks = (wave_tasks + p.waves - 1) / p.waves;
-    const int per_cu = knnf::persistent_blocks_per_cu(cfg);
-    const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(need_blocks,
-                                                  (uint64_t)ctx->num_cu * per_cu));
-    rc = knnf::launch_filter_batch((const knnf::FrameDesc*)s.dev,
-                                   (const uint32_t*)((char*)s.dev + off_ts), (uint32_t)n,
-                                   (uint32_t)total, d_ctr, cfg, (int)grid, stream);
-    if (rc != 0) return hip_fail((hipError_t)rc, "knnf_filter_batch launch");
-    e = hipEventRecord(s.done, hs);
-    if (e != hipSuccess) return hip_fail(e, "batch slot record");
-    s.recorded = true;
+    hipSetDevice(ctx->device);
+    unsigned long long h[2] = {0, 0};
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(h, ctx->d_stats, sizeof h, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && reset) e = hipMemset(ctx->d_stats, 0, sizeof h);
+    hipSetDevice(prev);
+    if (e != hipSuccess) return hip_fail(e, "knnf_stats_read");
+    *pairs = h[0];
+    *tiles = h[1];
     return KNNF_OK;
 }
 
@@ -359,7 +429,7 @@ knnf_status knnf_tune(knnf_ctx* ctx, const knnf_frame* frames, int n, int reps, 
     if (!ctx) return fail(KNNF_EINVAL, "knnf_tune: NULL context");
     if (n < 1 || !frames || reps < 1) return fail(KNNF_EINVAL, "knnf_tune: bad arguments");
     for (int i = 0; i < n; ++i) {
-        knnf_status st = validate(&frames[i], i);
+        knnf_status st = validate_impl(&frames[i], i);
         if (st != KNNF_OK) return st;
     }
     static const int ws[] = {1, 2, 4};
@@ -379,7 +449,7 @@ knnf_status knnf_tune(knnf_ctx* ctx, const knnf_frame* frames, int n, int reps, 
                 p.tile_rows = sh[0];
                 p.tile_cols = sh[1];
                 p.waves = w;
-                if (!plan_ok(p)) continue;
+                if (!plan_ok_impl(p)) continue;
                 auto run = [&]() -> knnf_status {
                     return n == 1 ? knnf_filter(ctx, frames, &p, stream)
                                   : knnf_filter_batch(ctx, frames, n, &p, stream);

@@ -17,13 +17,7 @@ struct FrameDesc {
     float* out_dist;      // [H][W][K] or null
     int32_t H, W, C, K, R;
     float lambda;
-};
-
-// Work accounting for the persistent batched launch: frame f owns the task
-// ids [task_start[f], task_start[f+1]); a task is one wavefront tile.
-struct BatchHeader {
-    uint32_t nframes;
-    uint32_t total_tasks;
+    unsigned long long* stats;  // [0] pairs evaluated, [1] tiles; null: not counted
 };
 
 // Kernel launch configuration chosen by the host (see knnf_plan).
@@ -37,8 +31,16 @@ struct LaunchCfg {
 // Host-side launchers (defined in knnf_kernels.hip).  Return hipError_t as int.
 int launch_filter_frame(const FrameDesc& f, const LaunchCfg& cfg, void* stream);
 int launch_filter_batch(const FrameDesc* d_frames, const uint32_t* d_task_start,
-                        uint32_t nframes, uint32_t total_tasks, uint32_t* d_counter,
-                        const LaunchCfg& cfg, int grid_blocks, void* stream);
+                        const uint32_t* d_tile_base, uint32_t nframes, uint32_t total_tasks,
+                        uint32_t* d_counter, const LaunchCfg& cfg, int grid_blocks, void* stream);
+int launch_zero_counter(uint32_t* d_counter, void* stream);
+
+// A range of tiles of one frame, the unit of a batched launch.
+struct WorkItem {
+    FrameDesc f;
+    uint32_t tile0;    // first tile (row-major over the frame's tile grid)
+    uint32_t ntiles;   // number of tiles
+};
 int persistent_blocks_per_cu(const LaunchCfg& cfg);
 
 }  // namespace knnf

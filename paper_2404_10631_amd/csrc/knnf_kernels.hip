@@ -51,6 +51,7 @@ constexpr int WAVE = 64;
 constexpr int A2ROWS = 64;  // window rows per block of the LDS a2 table
 constexpr int A2PAD = 4;    // padding rows (+inf) so a 4-row group may start anywhere
 constexpr int MAXC = 16;
+constexpr int CLAIM = 8;     // tasks claimed per atomic in the batched kernel
 
 __device__ __forceinline__ int lane_id() {
     return (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
@@ -429,6 +430,10 @@ __device__ __forceinline__ void process_tile(TileState<QR, QC>& S, const FrameDe
         wave_sync();
     }
 
+    // Work counter (only reported when f.stats is set): candidate distances
+    // evaluated for on-frame queries; pass A counts its 64 block slots.
+    unsigned long long pairs = (unsigned long long)(nqr * nqc) * WAVE;
+
     // Uniform per-query values live in VGPRs (read from LDS) to keep the
     // scalar register file free for loop state.  Queries off the frame have
     // iq = NaN and bound 0, so they never pass the test below.
@@ -552,6 +557,15 @@ __device__ __forceinline__ void process_tile(TileState<QR, QC>& S, const FrameDe
 #pragma unroll
                     for (int qr = 0; qr < QR; ++qr) a2[u][qr] = S.a2t[g + u][qr];
                 const int i0 = blk + g;
+                if (f.stats) {
+                    const int nvl = min(WAVE, W - J);
+#pragma unroll
+                    for (int qr = 0; qr < QR; ++qr) {
+                        const int r = r0 + qr;
+                        const int a = max(i0, max(lo, r - R)), z = min(i0 + 3, min(hi, r + R));
+                        if (qr < nqr && z >= a) pairs += (unsigned long long)(z - a + 1) * nqc * nvl;
+                    }
+                }
                 uint32_t ovf = 0;  // queries whose pending buffer could not take a row
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
@@ -725,6 +739,10 @@ __device__ __forceinline__ void process_tile(TileState<QR, QC>& S, const FrameDe
             f.out_class[(size_t)(r0 + qr) * W + c0 + qc] = best;
         }
     }
+    if (f.stats && L == 0) {
+        atomicAdd(&f.stats[0], pairs);
+        atomicAdd(&f.stats[1], 1ull);
+    }
     wave_sync();
 }
 
@@ -753,32 +771,45 @@ __global__ void __launch_bounds__(WPB * WAVE) filter_frame_kernel(FrameDesc f) {
 }
 
 // Persistent batched kernel: each wavefront claims tile tasks from a global
-// counter until all tasks of all frames are taken.  Every wavefront leaves the
-// loop after one failed claim, so the grid always drains.
+// counter until all tasks of all work items are taken.  Work item k is a range
+// of tiles of frames[k] starting at tile_base[k]; its tasks are the ids
+// task_start[k] .. task_start[k+1]-1.  Every wavefront leaves the loop after
+// one failed claim, so the grid always drains.
 template <int QR, int QC, int WPB, bool PRUNE>
 __global__ void __launch_bounds__(WPB * WAVE)
 filter_batch_kernel(const FrameDesc* __restrict__ frames, const uint32_t* __restrict__ task_start,
-                    uint32_t nframes, uint32_t total_tasks, uint32_t* counter) {
+                    const uint32_t* __restrict__ tile_base, uint32_t nframes, uint32_t total_tasks,
+                    uint32_t* counter) {
     __shared__ TileState<QR, QC> lds[WPB];
     const int w = uni((int)(threadIdx.x >> 6));
     const int L = lane_id();
     for (;;) {
-        uint32_t t = 0;
-        if (L == 0) t = atomicAdd(counter, 1u);
-        t = uniu(t);  // lane 0's claim
-        if (t >= total_tasks) break;
-        // frame f with task_start[f] <= t < task_start[f+1]
-        uint32_t lo = 0, hi = nframes;
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (task_start[mid] <= t) lo = mid; else hi = mid;
+        // claim CLAIM consecutive tasks: fewer atomics, and neighbouring tiles
+        // (which share window rows) stay on one wavefront
+        uint32_t t0 = 0;
+        if (L == 0) t0 = atomicAdd(counter, (uint32_t)CLAIM);
+        t0 = uniu(t0);  // lane 0's claim
+        if (t0 >= total_tasks) break;
+        const uint32_t t1 = min(total_tasks, t0 + (uint32_t)CLAIM);
+        uint32_t k = 0, next = 0;  // work item of the current task, its end
+        for (uint32_t t = t0; t < t1; ++t) {
+            if (t >= next || t == t0) {
+                // work item k with task_start[k] <= t < task_start[k+1]
+                uint32_t lo = 0, hi = nframes;
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (task_start[mid] <= t) lo = mid; else hi = mid;
+                }
+                k = lo;
+                next = task_start[k + 1];
+            }
+            const FrameDesc f = frames[k];
+            const uint32_t s = t - task_start[k] + tile_base[k];
+            const uint32_t ntc = (uint32_t)((f.W + QC - 1) / QC);
+            const int band = (int)(s / ntc);
+            const int tc = (int)(s - (uint32_t)band * ntc);
+            process_tile<QR, QC, PRUNE>(lds[w], f, band * QR, tc * QC);
         }
-        const FrameDesc f = frames[lo];
-        const uint32_t s = t - task_start[lo];
-        const uint32_t ntc = (uint32_t)((f.W + QC - 1) / QC);
-        const int band = (int)(s / ntc);
-        const int tc = (int)(s - (uint32_t)band * ntc);
-        process_tile<QR, QC, PRUNE>(lds[w], f, band * QR, tc * QC);
     }
 }
 
@@ -792,10 +823,10 @@ int launch_frame_t(const FrameDesc& f, hipStream_t st) {
 }
 
 template <int QR, int QC, int WPB, bool PRUNE>
-int launch_batch_t(const FrameDesc* fr, const uint32_t* ts, uint32_t n, uint32_t tot,
-                   uint32_t* ctr, int grid, hipStream_t st) {
+int launch_batch_t(const FrameDesc* fr, const uint32_t* ts, const uint32_t* tb, uint32_t n,
+                   uint32_t tot, uint32_t* ctr, int grid, hipStream_t st) {
     hipLaunchKernelGGL((filter_batch_kernel<QR, QC, WPB, PRUNE>), dim3((unsigned)grid),
-                       dim3(WPB * WAVE), 0, st, fr, ts, n, tot, ctr);
+                       dim3(WPB * WAVE), 0, st, fr, ts, tb, n, tot, ctr);
     return (int)hipGetLastError();
 }
 
@@ -839,11 +870,11 @@ int launch_filter_frame(const FrameDesc& f, const LaunchCfg& cfg, void* stream) 
 }
 
 int launch_filter_batch(const FrameDesc* d_frames, const uint32_t* d_task_start,
-                        uint32_t nframes, uint32_t total_tasks, uint32_t* d_counter,
-                        const LaunchCfg& cfg, int grid_blocks, void* stream) {
+                        const uint32_t* d_tile_base, uint32_t nframes, uint32_t total_tasks,
+                        uint32_t* d_counter, const LaunchCfg& cfg, int grid_blocks, void* stream) {
     hipStream_t st = (hipStream_t)stream;
-    KNNF_DISPATCH(launch_batch_t, d_frames, d_task_start, nframes, total_tasks, d_counter,
-                  grid_blocks, st);
+    KNNF_DISPATCH(launch_batch_t, d_frames, d_task_start, d_tile_base, nframes, total_tasks,
+                  d_counter, grid_blocks, st);
 }
 
 int persistent_blocks_per_cu(const LaunchCfg& cfg) { KNNF_DISPATCH(occupancy_t); }

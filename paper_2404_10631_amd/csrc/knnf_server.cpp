@@ -1,0 +1,450 @@
+// knnf_server.cpp -- continuous-batching server behind the knnf_server_* C-ABI.
+//
+// Frames arrive from the host at any time.  A scheduler thread
+//   1. admits queued frames in arrival order while the caller's device pool
+//      has room (first-fit sub-allocation; the head of the queue is never
+//      overtaken, so no frame starves) and copies their inputs to the pool on
+//      a copy stream;
+//   2. builds GPU steps: one batched launch over tile ranges of all admitted
+//      frames in arrival order, up to a tile budget, so a large frame is
+//      processed in slices and later arrivals join the next step; up to
+//      `max_inflight` steps are queued on separate compute streams;
+//   3. watches step completion events and marks a frame done when the last
+//      step holding its tiles has finished.
+// In plain mode each step is one whole frame, launched alone (the baseline).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/knnf.h"
+#include "knnf_device.h"
+#include "knnf_internal.h"
+
+namespace {
+
+double now_s() {
+    using clk = std::chrono::steady_clock;
+    return std::chrono::duration<double>(clk::now().time_since_epoch()).count();
+}
+
+size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// First-fit allocator over [0, size) with coalescing of free neighbours.
+class PoolAllocator {
+   public:
+    explicit PoolAllocator(size_t size) : size_(size) { free_[0] = size; }
+    bool alloc(size_t bytes, size_t* off) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes;
+                const size_t start = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[start] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t size() const { return size_; }
+
+   private:
+    size_t size_;
+    std::map<size_t, size_t> free_;
+};
+
+enum JobState { QUEUED, ADMITTED, DONE, RELEASED };
+
+struct Job {
+    uint64_t ticket = 0;
+    knnf_host_frame hf{};
+    JobState state = QUEUED;
+    size_t off = 0, bytes = 0;
+    knnf_frame dev{};
+    uint32_t ntiles = 0, next_tile = 0;
+    int outstanding = 0;          // launched steps holding tiles of this job
+    bool waited = false;          // compute streams were told to wait for its copy
+    hipEvent_t copied = nullptr;  // inputs are in the pool
+    double t_arrival = 0, t_admit = 0, t_launch = -1, t_done = 0;
+};
+
+struct Step {
+    hipEvent_t done = nullptr;
+    hipStream_t stream = nullptr;
+    bool active = false;
+    std::vector<uint64_t> tickets;  // jobs with tiles in this step
+};
+
+}  // namespace
+
+struct knnf_server {
+    knnf_ctx* ctx = nullptr;
+    int device = 0;
+    char* pool = nullptr;
+    knnf_server_opts opts{};
+    knnf_plan plan{};
+    PoolAllocator alloc{0};
+    hipStream_t copy_stream = nullptr;
+    std::vector<Step> steps;
+    std::vector<hipEvent_t> event_pool;
+
+    std::mutex mu;
+    std::condition_variable cv;
+    std::unordered_map<uint64_t, Job> jobs;
+    std::deque<uint64_t> queue;   // submitted, not admitted
+    std::deque<uint64_t> ready;   // admitted, tiles left to launch
+    uint64_t next_ticket = 1;
+    size_t unfinished = 0;
+    std::atomic<bool> stop{false};
+    std::thread thread;
+    knnf_status sticky = KNNF_OK;
+
+    explicit knnf_server(size_t pool_bytes) : alloc(pool_bytes) {}
+};
+
+namespace {
+
+hipEvent_t take_event(knnf_server* s) {
+    if (!s->event_pool.empty()) {
+        hipEvent_t e = s->event_pool.back();
+        s->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Lay out a frame in the pool: inputs, then outputs, 256-byte aligned.
+void place(Job& j, char* base) {
+    const size_t px = (size_t)j.hf.H * (size_t)j.hf.W;
+    size_t o = j.off;
+    auto put = [&](size_t bytes) {
+        char* p = base + o;
+        o += round256(bytes);
+        return p;
+    };
+    knnf_frame& d = j.dev;
+    d.H = j.hf.H;
+    d.W = j.hf.W;
+    d.C = j.hf.C;
+    d.K = j.hf.K;
+    d.R = j.hf.R;
+    d.lambda = j.hf.lambda;
+    d.pc1 = (const float*)put(px * 4);
+    d.prob = (const float*)put(px * j.hf.C * 4);
+    d.out_prob = (float*)put(px * j.hf.C * 4);
+    d.out_class = (int32_t*)put(px * 4);
+    d.out_nbr = j.hf.with_nbr ? (int32_t*)put(px * j.hf.K * 4) : nullptr;
+    d.out_dist = j.hf.with_nbr ? (float*)put(px * j.hf.K * 4) : nullptr;
+}
+
+// Admission: FIFO while the pool has room.  Called with the lock held.
+void admit(knnf_server* s) {
+    while (!s->queue.empty()) {
+        Job& j = s->jobs[s->queue.front()];
+        size_t off = 0;
+        if (!s->alloc.alloc(j.bytes, &off)) return;
+        j.off = off;
+        place(j, s->pool);
+        const size_t px = (size_t)j.hf.H * (size_t)j.hf.W;
+        hipError_t e = hipMemcpyAsync((void*)j.dev.pc1, j.hf.pc1, px * 4, hipMemcpyHostToDevice,
+                                      s->copy_stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync((void*)j.dev.prob, j.hf.prob, px * j.hf.C * 4,
+                               hipMemcpyHostToDevice, s->copy_stream);
+        j.copied = take_event(s);
+        if (e == hipSuccess && j.copied) e = hipEventRecord(j.copied, s->copy_stream);
+        if (e != hipSuccess || !j.copied) {
+            s->sticky = KNNF_EDEVICE;
+            return;
+        }
+        j.state = ADMITTED;
+        j.t_admit = now_s();
+        j.ntiles = knnf::tiles_of(j.hf.H, j.hf.W, s->plan);
+        s->queue.pop_front();
+        s->ready.push_back(j.ticket);
+    }
+}
+
+void finish_job(knnf_server* s, Job& j, double t) {
+    j.state = DONE;
+    j.t_done = t;
+    if (j.copied) {
+        s->event_pool.push_back(j.copied);
+        j.copied = nullptr;
+    }
+    --s->unfinished;
+}
+
+// Completion of queued steps.  Called with the lock held.
+bool reap(knnf_server* s) {
+    bool any = false;
+    for (Step& st : s->steps) {
+        if (!st.active) continue;
+        const hipError_t q = hipEventQuery(st.done);
+        if (q == hipErrorNotReady) continue;
+        if (q != hipSuccess) s->sticky = KNNF_EDEVICE;
+        const double t = now_s();
+        for (uint64_t tk : st.tickets) {
+            Job& j = s->jobs[tk];
+            if (--j.outstanding == 0 && j.next_tile == j.ntiles) finish_job(s, j, t);
+        }
+        st.tickets.clear();
+        st.active = false;
+        any = true;
+    }
+    return any;
+}
+
+// Build and enqueue one step on a free stream.  Called with the lock held.
+bool launch_step(knnf_server* s) {
+    if (s->ready.empty()) return false;
+    Step* st = nullptr;
+    for (Step& x : s->steps)
+        if (!x.active) {
+            st = &x;
+            break;
+        }
+    if (!st) return false;
+    const bool plain = s->opts.mode == KNNF_SERVE_PLAIN;
+    std::vector<knnf::WorkItem> items;
+    uint64_t budget = plain ? ~0ull : (uint64_t)s->opts.step_tiles;
+    while (!s->ready.empty() && budget > 0) {
+        Job& j = s->jobs[s->ready.front()];
+        const uint32_t left = j.ntiles - j.next_tile;
+        const uint32_t take = (uint32_t)std::min<uint64_t>(left, budget);
+        if (!j.waited) {
+            if (hipStreamWaitEvent(st->stream, j.copied, 0) != hipSuccess) s->sticky = KNNF_EDEVICE;
+            j.waited = true;
+        }
+        knnf::WorkItem w;
+        w.f = knnf::desc_of(j.dev);
+        w.tile0 = j.next_tile;
+        w.ntiles = take;
+        items.push_back(w);
+        j.next_tile += take;
+        ++j.outstanding;
+        if (j.t_launch < 0) j.t_launch = now_s();
+        st->tickets.push_back(j.ticket);
+        budget -= take;
+        if (j.next_tile == j.ntiles) s->ready.pop_front();
+        if (plain) break;
+    }
+    knnf_status rc;
+    if (plain) {
+        rc = knnf_filter(s->ctx, &s->jobs[st->tickets[0]].dev, &s->plan, st->stream);
+    } else {
+        rc = knnf::launch_items(s->ctx, items.data(), (int)items.size(), s->plan, st->stream);
+    }
+    if (rc != KNNF_OK || hipEventRecord(st->done, st->stream) != hipSuccess) s->sticky = KNNF_EDEVICE;
+    st->active = true;
+    return true;
+}
+
+void scheduler(knnf_server* s) {
+    hipSetDevice(s->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    while (!s->stop.load()) {
+        bool progress = reap(s);
+        admit(s);
+        while (launch_step(s)) progress = true;
+        if (!progress) {
+            // Nothing completed or launched: wait briefly for a submission or
+            // for GPU progress (completion is observed by polling events).
+            s->cv.wait_for(lk, std::chrono::microseconds(20));
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+double knnf_server_clock(void) { return now_s(); }
+
+knnf_status knnf_server_create(knnf_server** out, knnf_ctx* ctx, void* pool, size_t pool_bytes,
+                               const knnf_server_opts* opts) {
+    if (!out || !ctx || !pool || pool_bytes < 4096)
+        return knnf::set_error(KNNF_EINVAL, "knnf_server_create: bad arguments");
+    *out = nullptr;
+    knnf_server_opts o{};
+    if (opts) o = *opts;
+    if (o.mode != KNNF_SERVE_BATCHED && o.mode != KNNF_SERVE_PLAIN)
+        return knnf::set_error(KNNF_EINVAL, "knnf_server_create: bad mode");
+    if (o.max_queue <= 0) o.max_queue = 4096;
+    if (o.max_inflight <= 0) o.max_inflight = 2;
+    if (o.max_inflight > 4) return knnf::set_error(KNNF_EINVAL, "max_inflight above 4");
+    if (o.step_tiles <= 0) o.step_tiles = 32768;
+    if (o.mode == KNNF_SERVE_PLAIN) o.max_inflight = 1;
+    const knnf_plan p = knnf::resolve_plan(ctx, &o.plan);
+    if (!knnf::plan_valid(p)) return knnf::set_error(KNNF_EINVAL, "knnf_server_create: bad plan");
+
+    knnf_server* s = new (std::nothrow) knnf_server(pool_bytes);
+    if (!s) return knnf::set_error(KNNF_ENOMEM, "knnf_server_create: out of host memory");
+    s->ctx = ctx;
+    s->device = knnf::ctx_device(ctx);
+    s->pool = (char*)pool;
+    s->opts = o;
+    s->plan = p;
+    int prev = 0;
+    hipGetDevice(&prev);
+    hipSetDevice(s->device);
+    bool ok = hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking) == hipSuccess;
+    s->steps.resize(o.max_inflight);
+    for (Step& st : s->steps) {
+        ok = ok && hipStreamCreateWithFlags(&st.stream, hipStreamNonBlocking) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&st.done, hipEventDisableTiming) == hipSuccess;
+    }
+    hipSetDevice(prev);
+    if (!ok) {
+        knnf_server_destroy(s);
+        return knnf::set_error(KNNF_EDEVICE, "knnf_server_create: stream or event creation failed");
+    }
+    s->thread = std::thread(scheduler, s);
+    *out = s;
+    return KNNF_OK;
+}
+
+knnf_status knnf_server_submit(knnf_server* s, const knnf_host_frame* f, uint64_t* ticket) {
+    if (!s || !f || !ticket) return knnf::set_error(KNNF_EINVAL, "knnf_server_submit: NULL argument");
+    knnf_frame v{};
+    v.H = f->H;
+    v.W = f->W;
+    v.C = f->C;
+    v.K = f->K;
+    v.R = f->R;
+    v.lambda = f->lambda;
+    v.pc1 = f->pc1;
+    v.prob = f->prob;
+    v.out_prob = (float*)1;    // placed in the pool on admission
+    v.out_class = (int32_t*)1;
+    knnf_status st = knnf::validate_frame(&v, 0);
+    if (st != KNNF_OK) return st;
+    const size_t bytes = knnf_frame_bytes(f->H, f->W, f->C, f->K, f->with_nbr ? 1 : 0);
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->sticky != KNNF_OK) return knnf::set_error(s->sticky, "server failed earlier");
+    if (bytes > s->alloc.size())
+        return knnf::set_error(KNNF_ENOMEM, "frame needs %zu bytes; pool has %zu", bytes,
+                               s->alloc.size());
+    if ((int)s->queue.size() >= s->opts.max_queue)
+        return knnf::set_error(KNNF_EAGAIN, "admission queue full");
+    Job j;
+    j.ticket = s->next_ticket++;
+    j.hf = *f;
+    j.bytes = bytes;
+    j.t_arrival = f->t_arrival >= 0 ? f->t_arrival : now_s();
+    s->jobs[j.ticket] = j;
+    s->queue.push_back(j.ticket);
+    ++s->unfinished;
+    *ticket = j.ticket;
+    s->cv.notify_one();
+    return KNNF_OK;
+}
+
+knnf_status knnf_server_poll(knnf_server* s, uint64_t ticket, knnf_ticket_info* info) {
+    if (!s || !info) return knnf::set_error(KNNF_EINVAL, "knnf_server_poll: NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->jobs.find(ticket);
+    if (it == s->jobs.end()) return knnf::set_error(KNNF_EINVAL, "unknown ticket");
+    const Job& j = it->second;
+    info->done = j.state == DONE || j.state == RELEASED;
+    info->released = j.state == RELEASED;
+    info->t_arrival = j.t_arrival;
+    info->t_admit = j.t_admit;
+    info->t_launch = j.t_launch;
+    info->t_done = j.t_done;
+    if (s->sticky != KNNF_OK) return knnf::set_error(s->sticky, "server failed");
+    return KNNF_OK;
+}
+
+knnf_status knnf_server_result(knnf_server* s, uint64_t ticket, knnf_frame* view) {
+    if (!s || !view) return knnf::set_error(KNNF_EINVAL, "knnf_server_result: NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->jobs.find(ticket);
+    if (it == s->jobs.end()) return knnf::set_error(KNNF_EINVAL, "unknown ticket");
+    if (it->second.state != DONE) return knnf::set_error(KNNF_ESTATE, "frame not done or released");
+    *view = it->second.dev;
+    return KNNF_OK;
+}
+
+knnf_status knnf_server_release(knnf_server* s, uint64_t ticket) {
+    if (!s) return knnf::set_error(KNNF_EINVAL, "knnf_server_release: NULL server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->jobs.find(ticket);
+    if (it == s->jobs.end()) return knnf::set_error(KNNF_EINVAL, "unknown ticket");
+    Job& j = it->second;
+    if (j.state != DONE) return knnf::set_error(KNNF_ESTATE, "frame not done");
+    s->alloc.release(j.off, j.bytes);
+    s->jobs.erase(it);
+    s->cv.notify_one();
+    return KNNF_OK;
+}
+
+knnf_status knnf_server_drain(knnf_server* s, double timeout_s) {
+    if (!s) return knnf::set_error(KNNF_EINVAL, "knnf_server_drain: NULL server");
+    const double t0 = now_s();
+    for (;;) {
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            if (s->sticky != KNNF_OK) return knnf::set_error(s->sticky, "server failed");
+            if (s->unfinished == 0) return KNNF_OK;
+        }
+        if (timeout_s > 0 && now_s() - t0 > timeout_s)
+            return knnf::set_error(KNNF_EAGAIN, "knnf_server_drain: timeout");
+        std::this_thread::sleep_for(std::chrono::microseconds(50));
+    }
+}
+
+knnf_status knnf_server_destroy(knnf_server* s) {
+    if (!s) return KNNF_OK;
+    s->stop.store(true);
+    s->cv.notify_all();
+    if (s->thread.joinable()) s->thread.join();
+    int prev = 0;
+    hipGetDevice(&prev);
+    hipSetDevice(s->device);
+    for (Step& st : s->steps) {
+        if (st.stream) {
+            hipStreamSynchronize(st.stream);
+            hipStreamDestroy(st.stream);
+        }
+        if (st.done) hipEventDestroy(st.done);
+    }
+    if (s->copy_stream) {
+        hipStreamSynchronize(s->copy_stream);
+        hipStreamDestroy(s->copy_stream);
+    }
+    for (auto& kv : s->jobs)
+        if (kv.second.copied) hipEventDestroy(kv.second.copied);
+    for (hipEvent_t e : s->event_pool) hipEventDestroy(e);
+    hipSetDevice(prev);
+    delete s;
+    return KNNF_OK;
+}
+
+}  // extern "C"

@@ -223,3 +223,28 @@ def test_single_hip_runtime_loaded(ctx):
     libs = {line.split()[-1] for line in maps.splitlines() if "libamdhip64" in line}
     assert len(libs) == 1, libs
     assert any("libknnf.so" in line for line in maps.splitlines())
+
+
+def test_work_counters(ctx):
+    """Exhaustive search evaluates every window pair (plus 64 pass-A block
+    slots per pixel); the pruned search evaluates fewer and gives the same
+    outputs."""
+    import torch
+
+    spec = inputs.FrameSpec("brain", 96, 150, 3, K=40, R=14)
+    pc1, prob = spec.make()
+    df = DeviceFrame(pc1, prob, spec.K, spec.R, spec.lam)
+    _lib.knnf_stats_enable(ctx, True)
+    try:
+        _lib.knnf_stats_read(ctx, reset=True)
+        _lib.knnf_filter(ctx, df.as_c(), EXH8, current_stream())
+        pe, te = _lib.knnf_stats_read(ctx, reset=True)
+        _lib.knnf_filter(ctx, df.as_c(), PRU8, current_stream())
+        pp, tp = _lib.knnf_stats_read(ctx, reset=True)
+    finally:
+        _lib.knnf_stats_enable(ctx, False)
+    torch.cuda.synchronize()
+    assert pe == spec.pairs() + 64 * spec.pixels
+    tiles = ((spec.H + 1) // 2) * ((spec.W + 7) // 8)
+    assert te == tp == tiles
+    assert pp < pe
