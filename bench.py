@@ -112,41 +112,61 @@ def batch_leg(ctx, plan, stream, reps=3):
     return out
 
 
-def serve_leg(ctx, plan, n_frames, rate):
+P99_TARGET_MS = 10.0   # pre-registered per-frame latency target of the served stream
+
+
+def serve_leg(ctx, plan, n_frames, rate, sweep=(1000.0, 2000.0, 4000.0, 5000.0, 6000.0, 7000.0, 8000.0),
+              sweep_frames=800):
     """Poisson stream of mixed frame sizes: continuous-batching server vs plain
-    one-frame-at-a-time launches, both fed by the same arrival schedule."""
+    one-frame-at-a-time launches, both fed by the same arrival schedules."""
     from paper_2404_10631_amd import _lib, inputs
     from paper_2404_10631_amd.serve import HostFrame, Server, replay, summarize
 
-    stream = inputs.serve_stream(n=n_frames, rate_hz=rate)
     # a pool of distinct frames per class, reused round-robin (same shapes and
     # statistics as drawing every frame afresh)
     distinct = {"S": 32, "M": 16, "L": 6}
     pool = {}
-    for cls, spec_kw in inputs.SERVE_CLASSES.items():
-        pool[cls] = []
-        for k in range(distinct[cls]):
-            fs = inputs.FrameSpec(spec_kw["gen"], spec_kw["H"], spec_kw["W"], 10000 + 97 * k,
-                                  K=spec_kw["K"], R=spec_kw["R"])
-            pool[cls].append(HostFrame(*fs.make(), fs.K, fs.R, fs.lam, cls=cls))
-    count = {c: 0 for c in pool}
-    frames, arrivals = [], []
-    for t, cls, _ in stream:
-        frames.append(pool[cls][count[cls] % len(pool[cls])])
-        count[cls] += 1
-        arrivals.append(t)
+    for cls, kw in inputs.SERVE_CLASSES.items():
+        pool[cls] = [HostFrame(*inputs.FrameSpec(kw["gen"], kw["H"], kw["W"], 10000 + 97 * k,
+                                                 K=kw["K"], R=kw["R"]).make(),
+                               kw["K"], kw["R"], 0.01, cls=cls)
+                     for k in range(distinct[cls])]
+
+    def schedule(n, hz, seed):
+        count = {c: 0 for c in pool}
+        frames, arrivals = [], []
+        for t, cls, _ in inputs.serve_stream(n=n, rate_hz=hz, seed=seed):
+            frames.append(pool[cls][count[cls] % len(pool[cls])])
+            count[cls] += 1
+            arrivals.append(t)
+        return frames, arrivals, count
+
+    frames, arrivals, mix = schedule(n_frames, rate, 5)
     warm = min(100, n_frames // 10)
     pool_bytes = 2 << 30
-    res = {}
+    res = {"p99_target_ms": P99_TARGET_MS}
     for name, mode in (("served", _lib.KNNF_SERVE_BATCHED), ("plain", _lib.KNNF_SERVE_PLAIN)):
         with Server(ctx, pool_bytes, mode=mode, plan=plan) as srv:
             r = replay(srv, frames, arrivals, warmup=warm, timeout_s=300)
             res[name] = summarize(frames, r, classes=list(pool))
-            # saturation: the same frames all at once
+            sweep_out = []
+            for hz in sweep:
+                f2, a2, _ = schedule(sweep_frames, hz, 6)
+                r2 = replay(srv, f2, a2, warmup=sweep_frames // 10, timeout_s=300)
+                sm = summarize(f2, r2)
+                sweep_out.append({"rate_hz": hz, "p50_ms": round(sm["p50_ms"], 4),
+                                  "p99_ms": round(sm["p99_ms"], 4),
+                                  "pixels_per_s": round(sm["pixels_per_s"], 1)})
+            res[name]["sweep"] = sweep_out
+            ok = [x for x in sweep_out if x["p99_ms"] <= P99_TARGET_MS]
+            res[name]["max_rate_meeting_p99_hz"] = max([rate] + [x["rate_hz"] for x in ok]) \
+                if res[name]["p99_ms"] <= P99_TARGET_MS else None
+            res[name]["pixels_per_s_at_p99_target"] = max(
+                [res[name]["pixels_per_s"]] + [x["pixels_per_s"] for x in ok])
+            # saturation: a burst of frames all at once
             nb = min(len(frames), 400)
-            r2 = replay(srv, frames[:nb], [0.0] * nb, timeout_s=300)
-            res[name]["saturated_pixels_per_s"] = summarize(frames[:nb], r2)["pixels_per_s"]
-    mix = {c: count[c] for c in count}
+            r3 = replay(srv, frames[:nb], [0.0] * nb, timeout_s=300)
+            res[name]["saturated_pixels_per_s"] = round(summarize(frames[:nb], r3)["pixels_per_s"], 1)
     res["stream"] = {"frames": n_frames, "rate_hz": rate, "mix": mix, "warmup_frames": warm,
                      "offered_pixels_per_s": round(sum(f.pixels for f in frames) /
                                                    max(arrivals[-1], 1e-9), 1)}

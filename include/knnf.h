@@ -115,7 +115,8 @@ typedef enum { KNNF_SEARCH_EXHAUSTIVE = 0, KNNF_SEARCH_PRUNED = 1 } knnf_search;
  *   tile_rows     query pixels per wavefront task = tile_rows x tile_cols;
  *   tile_cols     supported tiles (rows x cols): 1x8, 1x16, 2x4, 2x8, 4x4
  *   waves         wavefronts per workgroup; 1, 2 or 4
- * A zero tile or wave field means "the context's default" (initially a pruned
+ *   launch        knnf_launch (batched launches only)
+ * A zero tile, wave or launch field means "the context's default" (initially a pruned
  * search with 2 x 4 tiles and one wavefront per workgroup); search is always
  * taken from the plan (0 = exhaustive).
  */
@@ -124,7 +125,18 @@ typedef struct {
     int32_t tile_rows;
     int32_t tile_cols;
     int32_t waves;
+    int32_t launch;  /* batched launches: knnf_launch                            */
 } knnf_plan;
+
+/*
+ * How a batched launch distributes tile tasks.
+ *   KNNF_LAUNCH_PERSISTENT  a grid sized to the device; wavefronts claim
+ *                           consecutive tasks from a counter until none is left
+ *   KNNF_LAUNCH_GRID        one wavefront per task; the hardware dispatcher
+ *                           balances the load
+ * 0 means the context's default (persistent).
+ */
+typedef enum { KNNF_LAUNCH_DEFAULT = 0, KNNF_LAUNCH_PERSISTENT = 1, KNNF_LAUNCH_GRID = 2 } knnf_launch;
 
 /* Create a context on HIP device `device` (ordinal).  *out is NULL on error. */
 knnf_status knnf_create(knnf_ctx** out, int device);
@@ -214,7 +226,8 @@ typedef struct {
     int32_t max_queue;     /* frames submitted but not admitted; 0: 4096         */
     int32_t max_inflight;  /* GPU steps queued at once (batched mode), 0: 2; <=4 */
     int32_t step_tiles;    /* tile budget of one batched step; 0: 32768          */
-    knnf_plan plan;        /* kernel plan; zero fields: the context's default    */
+    knnf_plan plan;        /* kernel plan; zero fields: the context's default,    */
+                           /* except launch, which defaults to KNNF_LAUNCH_GRID   */
 } knnf_server_opts;
 
 typedef struct {

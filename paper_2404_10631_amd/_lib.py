@@ -44,13 +44,27 @@ class knnf_frame(ctypes.Structure):
     ]
 
 
+KNNF_LAUNCH_DEFAULT = 0
+KNNF_LAUNCH_PERSISTENT = 1
+KNNF_LAUNCH_GRID = 2
+
+
 class knnf_plan(ctypes.Structure):
     _fields_ = [("search", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
-                ("tile_cols", ctypes.c_int32), ("waves", ctypes.c_int32)]
+                ("tile_cols", ctypes.c_int32), ("waves", ctypes.c_int32),
+                ("launch", ctypes.c_int32)]
 
     def as_dict(self):
         return {"search": self.search, "tile_rows": self.tile_rows,
-                "tile_cols": self.tile_cols, "waves": self.waves}
+                "tile_cols": self.tile_cols, "waves": self.waves, "launch": self.launch}
+
+
+def make_plan(plan) -> "knnf_plan":
+    if isinstance(plan, knnf_plan):
+        return plan
+    return knnf_plan(int(plan.get("search", 0)), int(plan.get("tile_rows", 0)),
+                     int(plan.get("tile_cols", 0)), int(plan.get("waves", 0)),
+                     int(plan.get("launch", 0)))
 
 
 KNNF_SERVE_BATCHED = 0
@@ -150,12 +164,7 @@ def check(status: int) -> None:
 def _plan_ptr(plan):
     if plan is None:
         return None
-    if isinstance(plan, dict):
-        p = knnf_plan(int(plan.get("search", 0)), int(plan.get("tile_rows", 0)),
-                      int(plan.get("tile_cols", 0)), int(plan.get("waves", 0)))
-    else:
-        p = plan
-    return ctypes.byref(p)
+    return ctypes.byref(make_plan(plan))
 
 
 def knnf_version() -> str:

@@ -82,6 +82,7 @@ knnf_plan default_plan() {
     p.tile_rows = 2;
     p.tile_cols = 4;
     p.waves = 1;
+    p.launch = KNNF_LAUNCH_PERSISTENT;
     return p;
 }
 
@@ -93,6 +94,7 @@ bool plan_ok_impl(const knnf_plan& p) {
     for (const auto& s : kShapes) shape |= (p.tile_rows == s[0] && p.tile_cols == s[1]);
     if (!shape) return false;
     if (p.waves != 1 && p.waves != 2 && p.waves != 4) return false;
+    if (p.launch != KNNF_LAUNCH_PERSISTENT && p.launch != KNNF_LAUNCH_GRID) return false;
     return true;
 }
 
@@ -103,6 +105,7 @@ knnf_plan resolve_impl(const knnf_ctx* ctx, const knnf_plan* p) {
         if (p->tile_rows) r.tile_rows = p->tile_rows;
         if (p->tile_cols) r.tile_cols = p->tile_cols;
         if (p->waves) r.waves = p->waves;
+        if (p->launch) r.launch = p->launch;
     }
     return r;
 }
@@ -113,6 +116,7 @@ knnf::LaunchCfg to_cfg(const knnf_plan& p) {
     c.cols = p.tile_cols;
     c.waves = p.waves;
     c.pruned = p.search == KNNF_SEARCH_PRUNED ? 1 : 0;
+    c.persistent = p.launch != KNNF_LAUNCH_GRID;
     return c;
 }
 
@@ -245,9 +249,21 @@ knnf_status launch_items(knnf_ctx* ctx, const WorkItem* items, int n, const knnf
     e = hipMemcpyAsync(s.dev, s.host, off_counter(s.cap), hipMemcpyHostToDevice, hs);
     if (e != hipSuccess) return hip_fail(e, "batch table copy");
     uint32_t* d_ctr = (uint32_t*)((char*)s.dev + off_counter(s.cap));
-    int rc = knnf::launch_zero_counter(d_ctr, stream);
-    if (rc != 0) return hip_fail((hipError_t)rc, "counter reset");
     const knnf::LaunchCfg cfg = to_cfg(p);
+    int rc;
+    if (!cfg.persistent) {
+        rc = knnf::launch_filter_items((const knnf::FrameDesc*)s.dev,
+                                       (const uint32_t*)((char*)s.dev + off_task_start(s.cap)),
+                                       (const uint32_t*)((char*)s.dev + off_tile_base(s.cap)),
+                                       (uint32_t)n, (uint32_t)total, cfg, stream);
+        if (rc != 0) return hip_fail((hipError_t)rc, "batched launch");
+        e = hipEventRecord(s.done, hs);
+        if (e != hipSuccess) return hip_fail(e, "batch slot record");
+        s.recorded = true;
+        return KNNF_OK;
+    }
+    rc = knnf::launch_zero_counter(d_ctr, stream);
+    if (rc != 0) return hip_fail((hipError_t)rc, "counter reset");
     const uint64_t need_blocks = (total + p.waves - 1) / p.waves;
     const int per_cu = knnf::persistent_blocks_per_cu(cfg);
     const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(need_blocks,
@@ -434,6 +450,7 @@ knnf_status knnf_tune(knnf_ctx* ctx, const knnf_frame* frames, int n, int reps, 
     }
     static const int ws[] = {1, 2, 4};
     static const int ss[] = {KNNF_SEARCH_EXHAUSTIVE, KNNF_SEARCH_PRUNED};
+    static const int ls[] = {KNNF_LAUNCH_PERSISTENT, KNNF_LAUNCH_GRID};
     hipStream_t hs = (hipStream_t)stream;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -443,12 +460,15 @@ knnf_status knnf_tune(knnf_ctx* ctx, const knnf_frame* frames, int n, int reps, 
     knnf_status result = KNNF_OK;
     for (int s : ss)
         for (const auto& sh : kShapes)
-            for (int w : ws) {
+            for (int w : ws)
+                for (int l : ls) {
+                if (n == 1 && l == KNNF_LAUNCH_GRID) continue;  // single frames ignore it
                 knnf_plan p{};
                 p.search = s;
                 p.tile_rows = sh[0];
                 p.tile_cols = sh[1];
                 p.waves = w;
+                p.launch = l;
                 if (!plan_ok_impl(p)) continue;
                 auto run = [&]() -> knnf_status {
                     return n == 1 ? knnf_filter(ctx, frames, &p, stream)

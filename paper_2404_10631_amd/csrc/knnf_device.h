@@ -26,6 +26,7 @@ struct LaunchCfg {
     int cols;      // tile columns
     int waves;     // wavefronts per workgroup: 1, 2, 4
     int pruned;    // 0 exhaustive, 1 pruned
+    int persistent;  // batched launches: 1 persistent claim loop, 0 one wavefront per task
 };
 
 // Host-side launchers (defined in knnf_kernels.hip).  Return hipError_t as int.
@@ -33,6 +34,7 @@ int launch_filter_frame(const FrameDesc& f, const LaunchCfg& cfg, void* stream);
 int launch_filter_batch(const FrameDesc* d_frames, const uint32_t* d_task_start,
                         const uint32_t* d_tile_base, uint32_t nframes, uint32_t total_tasks,
                         uint32_t* d_counter, const LaunchCfg& cfg, int grid_blocks, void* stream);
+// Zero the batched kernel's claim counter.
 int launch_zero_counter(uint32_t* d_counter, void* stream);
 
 // A range of tiles of one frame, the unit of a batched launch.
@@ -42,5 +44,9 @@ struct WorkItem {
     uint32_t ntiles;   // number of tiles
 };
 int persistent_blocks_per_cu(const LaunchCfg& cfg);
+// Non-persistent launch over the same work table: one wavefront per task.
+int launch_filter_items(const FrameDesc* d_frames, const uint32_t* d_task_start,
+                        const uint32_t* d_tile_base, uint32_t nframes, uint32_t total_tasks,
+                        const LaunchCfg& cfg, void* stream);
 
 }  // namespace knnf

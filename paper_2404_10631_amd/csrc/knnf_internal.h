@@ -22,8 +22,8 @@ bool plan_valid(const knnf_plan& p);
 FrameDesc desc_of(const knnf_frame& f);
 uint32_t tiles_of(int H, int W, const knnf_plan& p);
 
-// One persistent launch over the given tile ranges, in the given order, on
-// `stream`.  Items must be validated.  The work table goes through one of the
+// One launch over the given tile ranges, in the given order, on `stream`
+// (persistent claim loop or one wavefront per task, as p.launch says).  Items must be validated.  The work table goes through one of the
 // context's table slots (reused only after the launch that used it ended).
 knnf_status launch_items(knnf_ctx* ctx, const WorkItem* items, int n, const knnf_plan& p,
                          void* stream);

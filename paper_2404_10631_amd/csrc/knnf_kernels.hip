@@ -41,6 +41,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "knnf_device.h"
 
 namespace knnf {
@@ -51,7 +53,6 @@ constexpr int WAVE = 64;
 constexpr int A2ROWS = 64;  // window rows per block of the LDS a2 table
 constexpr int A2PAD = 4;    // padding rows (+inf) so a 4-row group may start anywhere
 constexpr int MAXC = 16;
-constexpr int CLAIM = 8;     // tasks claimed per atomic in the batched kernel
 
 __device__ __forceinline__ int lane_id() {
     return (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
@@ -770,27 +771,28 @@ __global__ void __launch_bounds__(WPB * WAVE) filter_frame_kernel(FrameDesc f) {
     process_tile<QR, QC, PRUNE>(lds[w], f, band * QR, tc * QC);
 }
 
-// Persistent batched kernel: each wavefront claims tile tasks from a global
+// Persistent batched kernel: each wavefront claims tile tasks from one global
 // counter until all tasks of all work items are taken.  Work item k is a range
 // of tiles of frames[k] starting at tile_base[k]; its tasks are the ids
-// task_start[k] .. task_start[k+1]-1.  Every wavefront leaves the loop after
-// one failed claim, so the grid always drains.
+// task_start[k] .. task_start[k+1]-1.  Claims go out in task order, so the
+// whole device sweeps neighbouring tiles (which share window rows) at the same
+// time.  Every wavefront leaves the loop after one failed claim, so the grid
+// always drains.
 template <int QR, int QC, int WPB, bool PRUNE>
 __global__ void __launch_bounds__(WPB * WAVE)
 filter_batch_kernel(const FrameDesc* __restrict__ frames, const uint32_t* __restrict__ task_start,
                     const uint32_t* __restrict__ tile_base, uint32_t nframes, uint32_t total_tasks,
-                    uint32_t* counter) {
+                    uint32_t claim, uint32_t* counter) {
     __shared__ TileState<QR, QC> lds[WPB];
     const int w = uni((int)(threadIdx.x >> 6));
     const int L = lane_id();
     for (;;) {
-        // claim CLAIM consecutive tasks: fewer atomics, and neighbouring tiles
-        // (which share window rows) stay on one wavefront
+        // claim `claim` consecutive tasks: fewer atomics on the counter
         uint32_t t0 = 0;
-        if (L == 0) t0 = atomicAdd(counter, (uint32_t)CLAIM);
+        if (L == 0) t0 = atomicAdd(counter, claim);
         t0 = uniu(t0);  // lane 0's claim
         if (t0 >= total_tasks) break;
-        const uint32_t t1 = min(total_tasks, t0 + (uint32_t)CLAIM);
+        const uint32_t t1 = min(total_tasks, t0 + claim);
         uint32_t k = 0, next = 0;  // work item of the current task, its end
         for (uint32_t t = t0; t < t1; ++t) {
             if (t >= next || t == t0) {
@@ -813,6 +815,41 @@ filter_batch_kernel(const FrameDesc* __restrict__ frames, const uint32_t* __rest
     }
 }
 
+// Non-persistent batched kernel over the same work table: one wavefront per
+// task, the hardware dispatcher balances the load, XCD-aware block order.
+template <int QR, int QC, int WPB, bool PRUNE>
+__global__ void __launch_bounds__(WPB * WAVE)
+filter_items_kernel(const FrameDesc* __restrict__ frames, const uint32_t* __restrict__ task_start,
+                    const uint32_t* __restrict__ tile_base, uint32_t nframes,
+                    uint32_t total_tasks) {
+    __shared__ TileState<QR, QC> lds[WPB];
+    const int w = uni((int)(threadIdx.x >> 6));
+    const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const uint64_t t64 = (uint64_t)b * WPB + w;
+    if (t64 >= total_tasks) return;
+    const uint32_t t = (uint32_t)t64;
+    uint32_t lo = 0, hi = nframes;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (task_start[mid] <= t) lo = mid; else hi = mid;
+    }
+    const FrameDesc f = frames[lo];
+    const uint32_t s = t - task_start[lo] + tile_base[lo];
+    const uint32_t ntc = (uint32_t)((f.W + QC - 1) / QC);
+    const int band = (int)(s / ntc);
+    const int tc = (int)(s - (uint32_t)band * ntc);
+    process_tile<QR, QC, PRUNE>(lds[w], f, band * QR, tc * QC);
+}
+
+template <int QR, int QC, int WPB, bool PRUNE>
+int launch_items_t(const FrameDesc* fr, const uint32_t* ts, const uint32_t* tb, uint32_t n,
+                   uint32_t tot, hipStream_t st) {
+    const uint64_t blocks = ((uint64_t)tot + WPB - 1) / WPB;
+    hipLaunchKernelGGL((filter_items_kernel<QR, QC, WPB, PRUNE>), dim3((unsigned)blocks),
+                       dim3(WPB * WAVE), 0, st, fr, ts, tb, n, tot);
+    return (int)hipGetLastError();
+}
+
 template <int QR, int QC, int WPB, bool PRUNE>
 int launch_frame_t(const FrameDesc& f, hipStream_t st) {
     const long long tiles = (long long)((f.H + QR - 1) / QR) * ((f.W + QC - 1) / QC);
@@ -825,8 +862,11 @@ int launch_frame_t(const FrameDesc& f, hipStream_t st) {
 template <int QR, int QC, int WPB, bool PRUNE>
 int launch_batch_t(const FrameDesc* fr, const uint32_t* ts, const uint32_t* tb, uint32_t n,
                    uint32_t tot, uint32_t* ctr, int grid, hipStream_t st) {
+    // at least four claims per resident wavefront, at most 8 tasks per claim
+    const uint64_t waves = (uint64_t)grid * WPB;
+    const uint32_t claim = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(8, tot / (waves * 4)));
     hipLaunchKernelGGL((filter_batch_kernel<QR, QC, WPB, PRUNE>), dim3((unsigned)grid),
-                       dim3(WPB * WAVE), 0, st, fr, ts, tb, n, tot, ctr);
+                       dim3(WPB * WAVE), 0, st, fr, ts, tb, n, tot, claim, ctr);
     return (int)hipGetLastError();
 }
 
@@ -879,10 +919,17 @@ int launch_filter_batch(const FrameDesc* d_frames, const uint32_t* d_task_start,
 
 int persistent_blocks_per_cu(const LaunchCfg& cfg) { KNNF_DISPATCH(occupancy_t); }
 
-__global__ void zero_u32_kernel(uint32_t* p) { *p = 0u; }
+int launch_filter_items(const FrameDesc* d_frames, const uint32_t* d_task_start,
+                        const uint32_t* d_tile_base, uint32_t nframes, uint32_t total_tasks,
+                        const LaunchCfg& cfg, void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    KNNF_DISPATCH(launch_items_t, d_frames, d_task_start, d_tile_base, nframes, total_tasks, st);
+}
+
+__global__ void zero_counter_kernel(uint32_t* p) { *p = 0u; }
 
 int launch_zero_counter(uint32_t* d_counter, void* stream) {
-    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(1), 0, (hipStream_t)stream, d_counter);
+    hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, (hipStream_t)stream, d_counter);
     return (int)hipGetLastError();
 }
 

@@ -301,6 +301,9 @@ knnf_status knnf_server_create(knnf_server** out, knnf_ctx* ctx, void* pool, siz
     if (o.max_inflight > 4) return knnf::set_error(KNNF_EINVAL, "max_inflight above 4");
     if (o.step_tiles <= 0) o.step_tiles = 32768;
     if (o.mode == KNNF_SERVE_PLAIN) o.max_inflight = 1;
+    // steps are bounded slices of work: one wavefront per task (the hardware
+    // dispatcher balances it) unless the caller asks otherwise
+    if (o.plan.launch == KNNF_LAUNCH_DEFAULT) o.plan.launch = KNNF_LAUNCH_GRID;
     const knnf_plan p = knnf::resolve_plan(ctx, &o.plan);
     if (!knnf::plan_valid(p)) return knnf::set_error(KNNF_EINVAL, "knnf_server_create: bad plan");
 

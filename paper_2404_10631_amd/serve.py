@@ -53,8 +53,7 @@ class Server:
         opts.mode, opts.max_queue = mode, max_queue
         opts.max_inflight, opts.step_tiles = max_inflight, step_tiles
         if plan is not None:
-            opts.plan = _lib.knnf_plan(int(plan.get("search", 0)), int(plan.get("tile_rows", 0)),
-                                       int(plan.get("tile_cols", 0)), int(plan.get("waves", 0)))
+            opts.plan = _lib.make_plan(plan)
         else:
             dp = _lib.knnf_get_default_plan(ctx)
             opts.plan = dp

@@ -38,7 +38,7 @@ def test_struct_layout_matches_header():
     # knnf_frame: 5 int32 + float, then 6 pointers (8-byte aligned) = 24 + 48
     assert ctypes.sizeof(_lib.knnf_frame) == 72
     assert _lib.knnf_frame.pc1.offset == 24
-    assert ctypes.sizeof(_lib.knnf_plan) == 16
+    assert ctypes.sizeof(_lib.knnf_plan) == 20
 
 
 def test_version(lib):
