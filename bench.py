@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--legs", default="plain,batch,serve",
                     help="comma list of: plain (headline), batch (uneven / small-frame "
                          "batches), serve (Poisson mixed stream)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy (to scale HBM counters)")
     ap.add_argument("--serve-frames", type=int, default=2000)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     return ap.parse_args()
@@ -186,6 +188,15 @@ def main():
     from paper_2404_10631_amd.frames import DeviceFrame, current_stream
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        n = 64 << 20  # 64 Mi float32 = 256 MiB read + 256 MiB written per copy
+        x = torch.rand(n, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 5}))
+        return
     spec = inputs.config1().frames[0]
     pc1, prob = spec.make()
     frame = DeviceFrame(pc1, prob, spec.K, spec.R, spec.lam, with_nbr=False)
@@ -236,7 +247,7 @@ def main():
     achieved = evaluated * FLOP_PER_PAIR / (kernel_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4),
-                "traffic": None,
+                "traffic": measured_traffic(plan),
                 "kernel": "filter_frame_kernel", "kernel_ms": round(kernel_ms, 5),
                 "work": f"{evaluated} evaluated pairs x {FLOP_PER_PAIR} FLOP",
                 "window_pairs": window_pairs,
@@ -283,6 +294,24 @@ def main():
         out["cpu_baseline"] = cpu_baseline(spec, pc1, prob, args.cpu_seconds)
     _lib.knnf_destroy(ctx)
     print(json.dumps(out), flush=True)
+
+
+def measured_traffic(plan):
+    """HBM bytes per launch of the timed kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE scaled by a plain copy), or None when the
+    kernel source or the plan changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "filter_frame_kernel_brain480x380_K40_traffic.txt")
+    src = os.path.join(ROOT, "paper_2404_10631_amd", "csrc", "knnf_kernels.hip")
+    try:
+        rec = json.loads(open(path).read().split("JSON:", 1)[1])
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, IndexError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != digest or rec.get("plan") != plan:
+        return None
+    return rec.get("traffic_bytes_per_launch")
 
 
 def spec_name(spec):
