@@ -344,6 +344,193 @@ __device__ __forceinline__ uint64_t flush_query(TileState<QR, QC>& S, const Fram
     return nl == K ? kth : KEY_INF;
 }
 
+// Pruned scan (bit-identical to the exhaustive one).  Every term of Eq. 1 is
+// >= 0 and binary32 rounding is monotone, so fmaf(b, b, a2) with the smallest
+// |b| and a2 of a set of candidates bounds all their distances from below;
+// a set whose bound exceeds every query's current bound tau cannot hold a
+// neighbour.  The scan visits the window in patches of 16 rows x 4 columns:
+// lane L holds row blk + (L & 15), column jc + (L >> 4), so a lane's row term
+// stays fixed while a row block is swept outward column step by column step.
+//   * live rows: rows where some query's row term alone is within its bound
+//     (its own column has b = 0);
+//   * per block of 16 live rows: the tile's own column steps, then steps to
+//     the right and to the left until the first step whose bound exceeds
+//     every query's (further steps only have larger column terms).
+// Survivors (d <= tau's distance) are appended per query with ballot +
+// mbcnt; a full buffer is merged into the query's sorted list, which
+// tightens its bound.
+template <int QR, int QC>
+__device__ __forceinline__ void scan_pruned(TileState<QR, QC>& S, const FrameDesc& f, int r0,
+                                            int c0, int nqr, int nqc,
+                                            const float (&iq)[QR * QC],
+                                            uint32_t (&th)[QR * QC], int (&cnt)[QR * QC],
+                                            unsigned long long& pairs) {
+    constexpr int Q = QR * QC;
+    const int L = lane_id();
+    const int H = f.H, W = f.W, R = f.R;
+    const float lam = f.lambda;
+    const float* __restrict__ pc1 = f.pc1;
+    const float pinf = __int_as_float(0x7f800000);
+    const int rlo = max(0, r0 - R), rhi = min(H - 1, r0 + nqr - 1 + R);
+
+    // ---- live rows
+    int lo = 0x7fffffff, hi = -1;
+    {
+        uint32_t thr[QR];  // loosest bound of each query row
+#pragma unroll
+        for (int qr = 0; qr < QR; ++qr) {
+            thr[qr] = th[qr * QC];
+#pragma unroll
+            for (int qc = 1; qc < QC; ++qc) thr[qr] = max(thr[qr], th[qr * QC + qc]);
+        }
+        for (int base = rlo; base <= rhi; base += WAVE) {
+            const int i = base + L;
+            const float fi = feat(lam, i);
+            bool live = false;
+#pragma unroll
+            for (int qr = 0; qr < QR; ++qr) {
+                const int r = r0 + qr;
+                const float a = feat(lam, r) - fi;
+                live |= qr < nqr && i <= rhi && i >= r - R && i <= r + R &&
+                        __float_as_uint(a * a) <= thr[qr];
+            }
+            const uint64_t m = ballot(live);
+            if (m) {
+                lo = min(lo, base + (int)__builtin_ctzll(m));
+                hi = max(hi, base + 63 - (int)__builtin_clzll(m));
+            }
+        }
+    }
+
+    const int lr = L & 15, lc = L >> 4;
+    const int ncen = (nqc + 3) >> 2;  // steps over the tile's own columns
+    for (int blk = lo; blk <= hi; blk += 16) {
+        const int bhi = min(blk + 15, hi);
+        const int i = blk + lr;
+        float a2[QR];   // this lane's row term per query row
+        bool rok[QR];   // this lane's row is live and in the query row's window
+        float a2n[QR];  // smallest row term of the block per query row (uniform)
+#pragma unroll
+        for (int qr = 0; qr < QR; ++qr) {
+            const int r = r0 + qr;
+            const float a = feat(lam, r) - feat(lam, i);
+            a2[qr] = a * a;
+            rok[qr] = qr < nqr && i <= bhi && i >= r - R && i <= r + R;
+            const int wl = max(blk, r - R), wh = min(bhi, r + R);
+            const float an = feat(lam, r) - feat(lam, min(max(r, wl), wh));
+            a2n[qr] = (qr < nqr && wl <= wh) ? an * an : pinf;
+        }
+        uint64_t rm[QR];  // lanes whose row is live and in the query row's window
+#pragma unroll
+        for (int qr = 0; qr < QR; ++qr) rm[qr] = ballot(rok[qr]);
+
+        // live column steps on each side: a prefix, found 64 steps at a time
+        int nside[2];
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            int n = 0;
+            for (;;) {
+                const int st = n + L;
+                const int jc = side == 0 ? c0 + 4 * (ncen + st) : c0 - 4 * (st + 1);
+                const int jn = side == 0 ? jc : jc + 3;  // the step's column nearest the tile
+                bool live = false;
+                if (side == 0 ? jc < W : jn >= 0) {
+                    const float fj = feat(lam, jn);
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) {
+                        const float b = feat(lam, c0 + q % QC) - fj;
+                        live |= __float_as_uint(fmaf(b, b, a2n[q / QC])) <= th[q];
+                    }
+                }
+                const uint64_t m = ballot(live);
+                const int k = (~m) ? (int)__builtin_ctzll(~m) : WAVE;
+                n += k;
+                if (k < WAVE) break;
+            }
+            nside[side] = n;
+        }
+        const int nright = nside[0], ns = ncen + nright + nside[1];
+
+        // rows past the frame or the window are loaded clamped and never pass
+        const float* __restrict__ rowp = pc1 + (size_t)min(i, rhi) * W;
+        auto step_col = [&](int st) {
+            return st < ncen + nright ? c0 + 4 * st : c0 - 4 * (st - ncen - nright + 1);
+        };
+        float ipn = rowp[min(max(step_col(0) + lc, 0), W - 1)];
+        for (int st = 0; st < ns; ++st) {
+            const int jc = step_col(st);
+            const float ip = ipn;
+            if (st + 1 < ns) ipn = rowp[min(max(step_col(st + 1) + lc, 0), W - 1)];
+            const int j = jc + lc;
+            const bool jok = j >= 0 && j < W;
+            const uint32_t idx = (uint32_t)i * (uint32_t)W + (uint32_t)j;
+            float b[QC];
+#pragma unroll
+            for (int qc = 0; qc < QC; ++qc) b[qc] = feat(lam, c0 + qc) - feat(lam, j);
+            const uint64_t jm = ballot(jok);
+            if (f.stats) {
+#pragma unroll
+                for (int qr = 0; qr < QR; ++qr)
+                    pairs += (unsigned long long)__builtin_popcountll(jm & rm[qr]) * nqc;
+            }
+            uint32_t ovf = 0;  // queries whose buffer cannot take this step's survivors
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int qr = q / QC, qc = q % QC;
+                const float e = iq[q] - ip;
+                const float d = fmaf(e, e, fmaf(b[qc], b[qc], a2[qr]));
+                const bool pass = jok && rok[qr] && __float_as_uint(d) <= th[q];
+                const uint64_t m = ballot(__float_as_uint(d) <= th[q]) & jm & rm[qr];
+                if (m) {
+                    const int n = __builtin_popcountll(m);
+                    if (cnt[q] + n <= WAVE) {
+                        if (pass) S.pend[q][cnt[q] + mbcnt(m)] = make_key(d, (int)idx);
+                        cnt[q] += n;
+                    } else {
+                        ovf |= 1u << q;
+                    }
+                }
+            }
+            if (ovf) {
+                // rare: merge the full buffers into the sorted lists (which
+                // tightens the bounds), then append this step's survivors
+#pragma unroll
+                for (int q = 0; q < Q; ++q)
+                    if (L == 0) S.cnt[q] = cnt[q];
+                wave_sync();
+                while (ovf) {
+                    const int q = __builtin_ctz(ovf);
+                    ovf &= ovf - 1;
+                    const int qr = q / QC, qc = q % QC;
+                    const int r = r0 + qr;
+                    const float a = feat(lam, r) - feat(lam, i);
+                    const float bq = feat(lam, c0 + qc) - feat(lam, j);
+                    const float e = S.iq[q] - ip;
+                    const float d = fmaf(e, e, fmaf(bq, bq, a * a));
+                    const bool rq = i <= bhi && i >= r - R && i <= r + R;
+                    const uint64_t kth = flush_query(S, f, r0, c0, q, uni(S.cnt[q]), false);
+                    uint32_t thq = uniu(S.tauhi[q]);
+                    if (kth != KEY_INF) thq = min(thq, (uint32_t)(kth >> 32));
+                    const bool pass = jok && rq && __float_as_uint(d) <= thq;
+                    const uint64_t m = ballot(pass);
+                    if (pass) S.pend[q][mbcnt(m)] = make_key(d, (int)idx);
+                    wave_sync();
+                    if (L == 0) {
+                        S.cnt[q] = __builtin_popcountll(m);
+                        S.tauhi[q] = thq;
+                    }
+                    wave_sync();
+                }
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    cnt[q] = uni(S.cnt[q]);
+                    th[q] = S.tauhi[q];
+                }
+            }
+        }
+    }
+}
+
 // Pass A: lane L's candidate in a compact block of query (r, c)'s window: 8 x 8
 // pixels where the window allows (fewer rows, more columns near short
 // windows); returns false for lanes past the frame's right edge.
@@ -448,219 +635,176 @@ __device__ __forceinline__ void process_tile(TileState<QR, QC>& S, const FrameDe
         cnt[q] = 0;
     }
 
-    // ---- pass B: window rows x 64-column chunks, nearest chunk first
-    const int rlo = max(0, r0 - R);
-    const int rhi = min(H - 1, r0 + nqr - 1 + R);
-    const int nch = (W + WAVE - 1) / WAVE;
-    const int cc = (c0 + (nqc - 1) / 2) / WAVE;
-    bool right_alive = true, left_alive = true;
-    int tab_base = -1;       // first row of the a2 table contents
-    uint32_t exact = 0;      // queries whose bound carries a real index (after a merge)
+    // ---- pass B
+    if constexpr (PRUNE) {
+        scan_pruned<QR, QC>(S, f, r0, c0, nqr, nqc, iq, th, cnt, pairs);
+    } else {
+        // exhaustive: window rows x 64-column chunks, nearest chunk first
+        const int rlo = max(0, r0 - R);
+        const int rhi = min(H - 1, r0 + nqr - 1 + R);
+        const int nch = (W + WAVE - 1) / WAVE;
+        const int cc = (c0 + (nqc - 1) / 2) / WAVE;
+        int tab_base = -1;       // first row of the a2 table contents
+        uint32_t exact = 0;      // queries whose bound carries a real index (after a merge)
 
-    for (int t = 0; t < 2 * nch; ++t) {
-        const int m = (t & 1) ? cc + (t + 1) / 2 : cc - t / 2;
-        if (m < 0 || m >= nch) continue;
-        if ((m > cc && !right_alive) || (m < cc && !left_alive)) continue;
-        const int J = m * WAVE;
-        const int j = J + L;
-        const bool valid = j < W;
-        const int jl = valid ? j : W - 1;
-        // lanes past the right edge get b = +inf, so every distance there is
-        // +inf (never below a finite bound; the append step checks `valid`)
-        float b[QC];
-#pragma unroll
-        for (int qc = 0; qc < QC; ++qc) b[qc] = valid ? feat(lam, c0 + qc) - feat(lam, j) : pinf;
+        for (int t = 0; t < 2 * nch; ++t) {
+            const int m = (t & 1) ? cc + (t + 1) / 2 : cc - t / 2;
+            if (m < 0 || m >= nch) continue;
+            const int J = m * WAVE;
+            const int j = J + L;
+            const bool valid = j < W;
+            const int jl = valid ? j : W - 1;
+            // lanes past the right edge get b = +inf, so every distance there is
+            // +inf (never below a finite bound; the append step checks `valid`)
+            float b[QC];
+    #pragma unroll
+            for (int qc = 0; qc < QC; ++qc) b[qc] = valid ? feat(lam, c0 + qc) - feat(lam, j) : pinf;
 
-        int lo = rlo, hi = rhi;
-        if (PRUNE) {
-            // Lower bound of Eq. 1 over the chunk for each query: the column
-            // term at the chunk column nearest the query plus the row term of
-            // the row; the spectral term is >= 0 and rounding is monotone.
-            // Keep the rows where some query could still reach its bound.
-            const int Je = min(J + WAVE - 1, W - 1);
-            float bmin[QC];
-#pragma unroll
-            for (int qc = 0; qc < QC; ++qc) {
-                const int cq = c0 + qc;
-                const int jn = cq < J ? J : (cq > Je ? Je : cq);
-                bmin[qc] = feat(lam, cq) - feat(lam, jn);
-            }
-            int nlo = 0x7fffffff, nhi = -1;
-            for (int base = rlo; base <= rhi; base += WAVE) {
-                const int i = base + L;
-                const float fi = feat(lam, i);
-                bool live = false;
-#pragma unroll
-                for (int qr = 0; qr < QR; ++qr) {
-                    const int r = r0 + qr;
-                    const float a = feat(lam, r) - fi;
-                    const float a2 = a * a;
-                    const bool inwin = qr < nqr && i <= rhi && i >= r - R && i <= r + R;
-#pragma unroll
-                    for (int qc = 0; qc < QC; ++qc) {
-                        const uint32_t lbd = __float_as_uint(fmaf(bmin[qc], bmin[qc], a2));
-                        live |= inwin && lbd <= th[qr * QC + qc];
-                    }
-                }
-                const uint64_t msk = ballot(live);
-                if (msk) {
-                    nlo = min(nlo, base + (int)__builtin_ctzll(msk));
-                    nhi = max(nhi, base + 63 - (int)__builtin_clzll(msk));
-                }
-            }
-            if (nhi < 0) {
-                // no query can gain here; chunks further out on this side have
-                // larger column terms for every query
-                if (m > cc) right_alive = false;
-                if (m < cc) left_alive = false;
-                continue;
-            }
-            lo = nlo;
-            hi = nhi;
-        }
+            const int lo = rlo, hi = rhi;
 
-        // Table blocks are aligned to rlo: block k holds rows rlo + 64k ...
-        // rlo + 64k + 63 (+inf past rhi and in the padding), so windows of up
-        // to 64 rows fill it once per tile.
-        for (int blk = rlo + ((lo - rlo) / A2ROWS) * A2ROWS; blk <= hi; blk += A2ROWS) {
-            if (blk != tab_base) {
-                wave_sync();
-                for (int u = L; u < (A2ROWS + A2PAD) * QR; u += WAVE) {
-                    const int rr = u / QR, qr = u % QR;
-                    const int r = r0 + qr, i = blk + rr;
-                    const bool act = rr < A2ROWS && qr < nqr && i <= rhi && i >= r - R && i <= r + R;
-                    const float a = feat(lam, r) - feat(lam, i);
-                    S.a2t[rr][qr] = act ? a * a : pinf;
-                }
-                wave_sync();
-                tab_base = blk;
-            }
-            const int g0 = max(lo, blk) - blk;
-            const int g1 = min(hi, blk + A2ROWS - 1) - blk;  // last table row used
-            const uint32_t joff = (uint32_t)jl;
-            const float* __restrict__ rowp = pc1 + (size_t)(blk + g0) * W;
-            float ipn[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                ipn[u] = rowp[(size_t)min(u, g1 - g0) * W + joff];
-            for (int g = g0; g <= g1; g += 4) {
-                float ip[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) ip[u] = ipn[u];
-                if (g + 4 <= g1) {
-                    const float* __restrict__ np = pc1 + (size_t)(blk + g + 4) * W;
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) ipn[u] = np[(size_t)min(u, g1 - g - 4) * W + joff];
-                }
-                float a2[4][QR];
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int qr = 0; qr < QR; ++qr) a2[u][qr] = S.a2t[g + u][qr];
-                const int i0 = blk + g;
-                if (f.stats) {
-                    const int nvl = min(WAVE, W - J);
-#pragma unroll
-                    for (int qr = 0; qr < QR; ++qr) {
-                        const int r = r0 + qr;
-                        const int a = max(i0, max(lo, r - R)), z = min(i0 + 3, min(hi, r + R));
-                        if (qr < nqr && z >= a) pairs += (unsigned long long)(z - a + 1) * nqc * nvl;
-                    }
-                }
-                uint32_t ovf = 0;  // queries whose pending buffer could not take a row
-#pragma unroll
-                for (int q = 0; q < Q; ++q) {
-                    const int qr = q / QC, qc = q % QC;
-                    float d[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const float e = iq[q] - ip[u];
-                        const float tt = fmaf(b[qc], b[qc], a2[u][qr]);
-                        d[u] = fmaf(e, e, tt);
-                    }
-                    const uint32_t mn = min(min(__float_as_uint(d[0]), __float_as_uint(d[1])),
-                                            min(__float_as_uint(d[2]), __float_as_uint(d[3])));
-                    if (ballot(mn <= th[q])) {
-                        // rare: some candidate of the group may belong to the
-                        // query.  Until the query's first merge its bound is
-                        // (d_K, max index), so key <= tau is d <= d_K; the
-                        // whole group is appended if it fits, otherwise (or
-                        // with an exact bound) the group goes to the merge path.
-                        const int r = r0 + qr;
-                        bool ok[4];
-                        uint64_t mu[4];
-                        int ntot = 0;
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const int i = i0 + u;
-                            const bool rowok = i <= hi && i >= r - R && i <= r + R;
-                            ok[u] = valid && rowok && __float_as_uint(d[u]) <= th[q];
-                            mu[u] = ballot(ok[u]);
-                            ntot += __builtin_popcountll(mu[u]);
-                        }
-                        if (((exact >> q) & 1u) || cnt[q] + ntot > WAVE) {
-                            ovf |= 1u << q;
-                        } else {
-#pragma unroll
-                            for (int u = 0; u < 4; ++u) {
-                                if (ok[u])
-                                    S.pend[q][cnt[q] + mbcnt(mu[u])] = make_key(d[u], (i0 + u) * W + j);
-                                cnt[q] += __builtin_popcountll(mu[u]);
-                            }
-                        }
-                    }
-                }
-                if (ovf) {
-                    // rare: merge full buffers and append the group exactly
-#pragma unroll
-                    for (int q = 0; q < Q; ++q)
-                        if (L == 0) S.cnt[q] = cnt[q];
+            // Table blocks are aligned to rlo: block k holds rows rlo + 64k ...
+            // rlo + 64k + 63 (+inf past rhi and in the padding), so windows of up
+            // to 64 rows fill it once per tile.
+            for (int blk = rlo + ((lo - rlo) / A2ROWS) * A2ROWS; blk <= hi; blk += A2ROWS) {
+                if (blk != tab_base) {
                     wave_sync();
-                    exact |= ovf;
-                    while (ovf) {
-                        const int q = __builtin_ctz(ovf);
-                        ovf &= ovf - 1;
-                        const int qr = q / QC, qc = q % QC;
-                        const int r = r0 + qr;
-                        int cq = uni(S.cnt[q]);
-                        uint64_t tq = uni64(S.tau[q]);
-                        const float bq = valid ? feat(lam, c0 + qc) - feat(lam, j) : pinf;
-                        const float iqq = S.iq[q];
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const int i = i0 + u;
-                            if (i > hi || i < r - R || i > r + R) continue;
-                            const float a2q = S.a2t[g + u][qr];
-                            const float e = iqq - ip[u];
-                            const float du = fmaf(e, e, fmaf(bq, bq, a2q));
-                            const int idx = i * W + j;
-                            bool ok = valid && make_key(du, idx) <= tq;
-                            uint64_t msk = ballot(ok);
-                            if (!msk) continue;
-                            int n = __builtin_popcountll(msk);
-                            if (cq + n > WAVE) {
-                                const uint64_t nb2 = flush_query(S, f, r0, c0, q, cq, false);
-                                cq = 0;
-                                tq = nb2 < tq ? nb2 : tq;
-                                ok = valid && make_key(du, idx) <= tq;
-                                msk = ballot(ok);
-                                n = __builtin_popcountll(msk);
-                            }
-                            if (ok) S.pend[q][cq + mbcnt(msk)] = make_key(du, idx);
-                            cq += n;
-                        }
-                        wave_sync();
-                        if (L == 0) {
-                            S.cnt[q] = cq;
-                            S.tau[q] = tq;
-                            S.tauhi[q] = (uint32_t)(tq >> 32);
-                        }
-                        wave_sync();
+                    for (int u = L; u < (A2ROWS + A2PAD) * QR; u += WAVE) {
+                        const int rr = u / QR, qr = u % QR;
+                        const int r = r0 + qr, i = blk + rr;
+                        const bool act = rr < A2ROWS && qr < nqr && i <= rhi && i >= r - R && i <= r + R;
+                        const float a = feat(lam, r) - feat(lam, i);
+                        S.a2t[rr][qr] = act ? a * a : pinf;
                     }
-#pragma unroll
+                    wave_sync();
+                    tab_base = blk;
+                }
+                const int g0 = max(lo, blk) - blk;
+                const int g1 = min(hi, blk + A2ROWS - 1) - blk;  // last table row used
+                const uint32_t joff = (uint32_t)jl;
+                const float* __restrict__ rowp = pc1 + (size_t)(blk + g0) * W;
+                float ipn[4];
+    #pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    ipn[u] = rowp[(size_t)min(u, g1 - g0) * W + joff];
+                for (int g = g0; g <= g1; g += 4) {
+                    float ip[4];
+    #pragma unroll
+                    for (int u = 0; u < 4; ++u) ip[u] = ipn[u];
+                    if (g + 4 <= g1) {
+                        const float* __restrict__ np = pc1 + (size_t)(blk + g + 4) * W;
+    #pragma unroll
+                        for (int u = 0; u < 4; ++u) ipn[u] = np[(size_t)min(u, g1 - g - 4) * W + joff];
+                    }
+                    float a2[4][QR];
+    #pragma unroll
+                    for (int u = 0; u < 4; ++u)
+    #pragma unroll
+                        for (int qr = 0; qr < QR; ++qr) a2[u][qr] = S.a2t[g + u][qr];
+                    const int i0 = blk + g;
+                    if (f.stats) {
+                        const int nvl = min(WAVE, W - J);
+    #pragma unroll
+                        for (int qr = 0; qr < QR; ++qr) {
+                            const int r = r0 + qr;
+                            const int a = max(i0, max(lo, r - R)), z = min(i0 + 3, min(hi, r + R));
+                            if (qr < nqr && z >= a) pairs += (unsigned long long)(z - a + 1) * nqc * nvl;
+                        }
+                    }
+                    uint32_t ovf = 0;  // queries whose pending buffer could not take a row
+    #pragma unroll
                     for (int q = 0; q < Q; ++q) {
-                        cnt[q] = uni(S.cnt[q]);
-                        th[q] = S.tauhi[q];
+                        const int qr = q / QC, qc = q % QC;
+                        float d[4];
+    #pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const float e = iq[q] - ip[u];
+                            const float tt = fmaf(b[qc], b[qc], a2[u][qr]);
+                            d[u] = fmaf(e, e, tt);
+                        }
+                        const uint32_t mn = min(min(__float_as_uint(d[0]), __float_as_uint(d[1])),
+                                                min(__float_as_uint(d[2]), __float_as_uint(d[3])));
+                        if (ballot(mn <= th[q])) {
+                            // rare: some candidate of the group may belong to the
+                            // query.  Until the query's first merge its bound is
+                            // (d_K, max index), so key <= tau is d <= d_K; the
+                            // whole group is appended if it fits, otherwise (or
+                            // with an exact bound) the group goes to the merge path.
+                            const int r = r0 + qr;
+                            bool ok[4];
+                            uint64_t mu[4];
+                            int ntot = 0;
+    #pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                const int i = i0 + u;
+                                const bool rowok = i <= hi && i >= r - R && i <= r + R;
+                                ok[u] = valid && rowok && __float_as_uint(d[u]) <= th[q];
+                                mu[u] = ballot(ok[u]);
+                                ntot += __builtin_popcountll(mu[u]);
+                            }
+                            if (((exact >> q) & 1u) || cnt[q] + ntot > WAVE) {
+                                ovf |= 1u << q;
+                            } else {
+    #pragma unroll
+                                for (int u = 0; u < 4; ++u) {
+                                    if (ok[u])
+                                        S.pend[q][cnt[q] + mbcnt(mu[u])] = make_key(d[u], (i0 + u) * W + j);
+                                    cnt[q] += __builtin_popcountll(mu[u]);
+                                }
+                            }
+                        }
+                    }
+                    if (ovf) {
+                        // rare: merge full buffers and append the group exactly
+    #pragma unroll
+                        for (int q = 0; q < Q; ++q)
+                            if (L == 0) S.cnt[q] = cnt[q];
+                        wave_sync();
+                        exact |= ovf;
+                        while (ovf) {
+                            const int q = __builtin_ctz(ovf);
+                            ovf &= ovf - 1;
+                            const int qr = q / QC, qc = q % QC;
+                            const int r = r0 + qr;
+                            int cq = uni(S.cnt[q]);
+                            uint64_t tq = uni64(S.tau[q]);
+                            const float bq = valid ? feat(lam, c0 + qc) - feat(lam, j) : pinf;
+                            const float iqq = S.iq[q];
+    #pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                const int i = i0 + u;
+                                if (i > hi || i < r - R || i > r + R) continue;
+                                const float a2q = S.a2t[g + u][qr];
+                                const float e = iqq - ip[u];
+                                const float du = fmaf(e, e, fmaf(bq, bq, a2q));
+                                const int idx = i * W + j;
+                                bool ok = valid && make_key(du, idx) <= tq;
+                                uint64_t msk = ballot(ok);
+                                if (!msk) continue;
+                                int n = __builtin_popcountll(msk);
+                                if (cq + n > WAVE) {
+                                    const uint64_t nb2 = flush_query(S, f, r0, c0, q, cq, false);
+                                    cq = 0;
+                                    tq = nb2 < tq ? nb2 : tq;
+                                    ok = valid && make_key(du, idx) <= tq;
+                                    msk = ballot(ok);
+                                    n = __builtin_popcountll(msk);
+                                }
+                                if (ok) S.pend[q][cq + mbcnt(msk)] = make_key(du, idx);
+                                cq += n;
+                            }
+                            wave_sync();
+                            if (L == 0) {
+                                S.cnt[q] = cq;
+                                S.tau[q] = tq;
+                                S.tauhi[q] = (uint32_t)(tq >> 32);
+                            }
+                            wave_sync();
+                        }
+    #pragma unroll
+                        for (int q = 0; q < Q; ++q) {
+                            cnt[q] = uni(S.cnt[q]);
+                            th[q] = S.tauhi[q];
+                        }
                     }
                 }
             }
