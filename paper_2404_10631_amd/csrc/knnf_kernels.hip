@@ -182,93 +182,166 @@ __device__ __forceinline__ uint32_t sort64_u32(uint32_t v) {
 
 // ---- segmented sorts: the Q queries of a tile sorted together.  Segment q
 // (64 elements) lives in lanes q*P .. q*P+P-1, P = 64 / E; lane L holds
-// elements e = (L % P) * E + r in x[r], r < E.  Partners e ^ d with d < E are
-// in the same lane (register pairs, no exchange); d >= E are in lane L ^ (d/E).
-template <int J>
-__device__ __forceinline__ uint64_t xlane64(uint64_t v) {
-    return ((uint64_t)xlane<J>((uint32_t)(v >> 32)) << 32) | (uint64_t)xlane<J>((uint32_t)v);
+// elements e = (L % P) * E + r in x[r], r < E.
+//
+// The network is the all-ascending form of the bitonic sort: stage KS first
+// compares e with its mirror e ^ (KS - 1) inside each block of KS elements
+// (both halves ascending -> the smaller KS/2 in the lower half, as two
+// bitonic halves), then half-cleaners compare e with e ^ D, D = KS/4 .. 1.
+// The lower element of every pair takes the minimum, so pairs inside a lane
+// need no direction, and cross-lane partners are lane ^ 1, 2, 3 or 7 for
+// E >= 8: all DPP lane permutations within a row.
+
+// Value of lane L ^ X (X in 1, 2, 3, 7, 15 via DPP; others via xlane).
+template <int X>
+__device__ __forceinline__ uint32_t lanex(uint32_t v) {
+    if constexpr (X == 1) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);  // quad_perm 1,0,3,2
+    } else if constexpr (X == 2) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);  // quad_perm 2,3,0,1
+    } else if constexpr (X == 3) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x1B, 0xF, 0xF, false);  // quad_perm 3,2,1,0
+    } else if constexpr (X == 7) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    } else if constexpr (X == 15) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, false);  // row_mirror
+    } else {
+        static_assert(X == 4 || X == 8 || X == 16 || X == 32, "unsupported lane permutation");
+        return xlane<X>(v);
+    }
+}
+template <int X>
+__device__ __forceinline__ uint64_t lanex64(uint64_t v) {
+    return ((uint64_t)lanex<X>((uint32_t)(v >> 32)) << 32) | (uint64_t)lanex<X>((uint32_t)v);
 }
 
-template <int E, int K_, int D>
-__device__ __forceinline__ void seg_step_key(uint64_t (&x)[E], int lp) {
+template <int E, int KS>
+__device__ __forceinline__ void seg_mirror_u32(uint32_t (&x)[E], int lp) {
+    if constexpr (KS <= E) {
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            if (r & (KS / 2)) continue;
+            constexpr int M = KS - 1;
+            const uint32_t a = x[r], b = x[r ^ M];
+            x[r] = min(a, b);
+            x[r ^ M] = max(a, b);
+        }
+    } else {
+        const bool upper = (lp & (KS / (2 * E))) != 0;
+        uint32_t p[E];
+#pragma unroll
+        for (int r = 0; r < E; ++r) p[r] = lanex<KS / E - 1>(x[E - 1 - r]);
+#pragma unroll
+        for (int r = 0; r < E; ++r) x[r] = upper ? max(x[r], p[r]) : min(x[r], p[r]);
+    }
+}
+
+template <int E, int D>
+__device__ __forceinline__ void seg_half_u32(uint32_t (&x)[E], int lp) {
     if constexpr (D < E) {
 #pragma unroll
         for (int r = 0; r < E; ++r) {
             if (r & D) continue;
-            // elements lp*E + r and lp*E + (r|D); descending block if bit K_ is set
-            const bool desc = (K_ < WAVE) && (((lp * E + r) & K_) != 0);
+            const uint32_t a = x[r], b = x[r | D];
+            x[r] = min(a, b);
+            x[r | D] = max(a, b);
+        }
+    } else {
+        const bool upper = (lp & (D / E)) != 0;
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const uint32_t p = lanex<D / E>(x[r]);
+            x[r] = upper ? max(x[r], p) : min(x[r], p);
+        }
+    }
+}
+
+template <int E, int KS, int D>
+__device__ __forceinline__ void seg_halves_u32(uint32_t (&x)[E], int lp) {
+    if constexpr (D >= 1) {
+        seg_half_u32<E, D>(x, lp);
+        seg_halves_u32<E, KS, D / 2>(x, lp);
+    }
+}
+
+template <int E, int KS>
+__device__ __forceinline__ void seg_stage_u32(uint32_t (&x)[E], int lp) {
+    seg_mirror_u32<E, KS>(x, lp);
+    seg_halves_u32<E, KS, KS / 4>(x, lp);
+    if constexpr (KS < WAVE) seg_stage_u32<E, KS * 2>(x, lp);
+}
+
+template <int E>
+__device__ __forceinline__ void seg_sort_u32(uint32_t (&x)[E], int lp) {
+    seg_stage_u32<E, 2>(x, lp);
+}
+
+// The same network over 64-bit keys (distance bits << 32 | index).
+template <int E, int KS>
+__device__ __forceinline__ void seg_mirror_key(uint64_t (&x)[E], int lp) {
+    if constexpr (KS <= E) {
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            if (r & (KS / 2)) continue;
+            constexpr int M = KS - 1;
+            const uint64_t a = x[r], b = x[r ^ M];
+            const bool sw = b < a;
+            x[r] = sw ? b : a;
+            x[r ^ M] = sw ? a : b;
+        }
+    } else {
+        const bool upper = (lp & (KS / (2 * E))) != 0;
+        uint64_t p[E];
+#pragma unroll
+        for (int r = 0; r < E; ++r) p[r] = lanex64<KS / E - 1>(x[E - 1 - r]);
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            const bool take = (p[r] < x[r]) != upper;
+            x[r] = take ? p[r] : x[r];
+        }
+    }
+}
+
+template <int E, int D>
+__device__ __forceinline__ void seg_half_key(uint64_t (&x)[E], int lp) {
+    if constexpr (D < E) {
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            if (r & D) continue;
             const uint64_t a = x[r], b = x[r | D];
-            const bool sw = (b < a) != desc;
+            const bool sw = b < a;
             x[r] = sw ? b : a;
             x[r | D] = sw ? a : b;
         }
     } else {
-        constexpr int LD = D / E;
-        const bool upper = (lp & LD) != 0;
+        const bool upper = (lp & (D / E)) != 0;
 #pragma unroll
         for (int r = 0; r < E; ++r) {
-            const bool desc = (K_ < WAVE) && (((lp * E + r) & K_) != 0);
-            const uint64_t p = xlane64<LD>(x[r]);
-            const bool take = (p < x[r]) != (upper != desc);
+            const uint64_t p = lanex64<D / E>(x[r]);
+            const bool take = (p < x[r]) != upper;
             x[r] = take ? p : x[r];
         }
     }
 }
 
-template <int E, int K_, int D>
+template <int E, int KS, int D>
+__device__ __forceinline__ void seg_halves_key(uint64_t (&x)[E], int lp) {
+    if constexpr (D >= 1) {
+        seg_half_key<E, D>(x, lp);
+        seg_halves_key<E, KS, D / 2>(x, lp);
+    }
+}
+
+template <int E, int KS>
 __device__ __forceinline__ void seg_stage_key(uint64_t (&x)[E], int lp) {
-    seg_step_key<E, K_, D>(x, lp);
-    if constexpr (D > 1) seg_stage_key<E, K_, D / 2>(x, lp);
+    seg_mirror_key<E, KS>(x, lp);
+    seg_halves_key<E, KS, KS / 4>(x, lp);
+    if constexpr (KS < WAVE) seg_stage_key<E, KS * 2>(x, lp);
 }
 
 template <int E>
 __device__ __forceinline__ void seg_sort_key(uint64_t (&x)[E], int lp) {
-    seg_stage_key<E, 2, 1>(x, lp);
-    seg_stage_key<E, 4, 2>(x, lp);
-    seg_stage_key<E, 8, 4>(x, lp);
-    seg_stage_key<E, 16, 8>(x, lp);
-    seg_stage_key<E, 32, 16>(x, lp);
-    seg_stage_key<E, 64, 32>(x, lp);
-}
-
-template <int E, int K_, int D>
-__device__ __forceinline__ void seg_step_u32(uint32_t (&x)[E], int lp) {
-    if constexpr (D < E) {
-#pragma unroll
-        for (int r = 0; r < E; ++r) {
-            if (r & D) continue;
-            const bool desc = (K_ < WAVE) && (((lp * E + r) & K_) != 0);
-            const uint32_t a = x[r], b = x[r | D];
-            const uint32_t lo = min(a, b), hi = max(a, b);
-            x[r] = desc ? hi : lo;
-            x[r | D] = desc ? lo : hi;
-        }
-    } else {
-        constexpr int LD = D / E;
-        const bool upper = (lp & LD) != 0;
-#pragma unroll
-        for (int r = 0; r < E; ++r) {
-            const bool desc = (K_ < WAVE) && (((lp * E + r) & K_) != 0);
-            const uint32_t p = xlane<LD>(x[r]);
-            x[r] = (upper != desc) ? max(x[r], p) : min(x[r], p);
-        }
-    }
-}
-
-template <int E, int K_, int D>
-__device__ __forceinline__ void seg_stage_u32(uint32_t (&x)[E], int lp) {
-    seg_step_u32<E, K_, D>(x, lp);
-    if constexpr (D > 1) seg_stage_u32<E, K_, D / 2>(x, lp);
-}
-
-template <int E>
-__device__ __forceinline__ void seg_sort_u32(uint32_t (&x)[E], int lp) {
-    seg_stage_u32<E, 2, 1>(x, lp);
-    seg_stage_u32<E, 4, 2>(x, lp);
-    seg_stage_u32<E, 8, 4>(x, lp);
-    seg_stage_u32<E, 16, 8>(x, lp);
-    seg_stage_u32<E, 32, 16>(x, lp);
-    seg_stage_u32<E, 64, 32>(x, lp);
+    seg_stage_key<E, 2>(x, lp);
 }
 
 // Per-wavefront LDS state of one tile of QR x QC query pixels.
@@ -848,25 +921,45 @@ __device__ __forceinline__ void process_tile(TileState<QR, QC>& S, const FrameDe
     }
     wave_sync();
 
-    // ---- Eq. 2: sums in neighbour order, one lane per (query, class)
-    const int npx = H * W;
-    const float* __restrict__ prob = f.prob;
+    // ---- Eq. 2: sums in neighbour order, one lane per (query, class).  The
+    // neighbours' rows are L2-resident; up to 16 gathers are in flight.
+    const uint32_t rowb = (uint32_t)C * 4u;  // bytes per probability row
     for (int p = L; p < Q * C; p += WAVE) {
         const int q = p / C, cl = p - q * C;
         const int qr = q / QC, qc = q % QC;
         if (qr >= nqr || qc >= nqc) continue;
+        const char* __restrict__ pb = (const char*)(f.prob + cl);
+        const uint32_t* lst = S.list[q];
         float s = 0.0f;
-        for (int k0 = 0; k0 < K; k0 += 16) {
+        int k = 0;
+        for (; k + 16 <= K; k += 16) {
             float v[16];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const uint32_t idx = (k0 + u < K) ? S.list[q][k0 + u] : 0xffffffffu;
-                v[u] = idx < (uint32_t)npx ? prob[(size_t)idx * C + cl] : 0.0f;
+            for (int u = 0; u < 16; u += 4) {
+                const uint4 id = *(const uint4*)(lst + k + u);
+                v[u + 0] = *(const float*)(pb + (uint64_t)id.x * rowb);
+                v[u + 1] = *(const float*)(pb + (uint64_t)id.y * rowb);
+                v[u + 2] = *(const float*)(pb + (uint64_t)id.z * rowb);
+                v[u + 3] = *(const float*)(pb + (uint64_t)id.w * rowb);
             }
 #pragma unroll
-            for (int u = 0; u < 16; ++u)
-                if (k0 + u < K) s = s + v[u];
+            for (int u = 0; u < 16; ++u) s = s + v[u];
         }
+        if (k + 8 <= K) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; u += 4) {
+                const uint4 id = *(const uint4*)(lst + k + u);
+                v[u + 0] = *(const float*)(pb + (uint64_t)id.x * rowb);
+                v[u + 1] = *(const float*)(pb + (uint64_t)id.y * rowb);
+                v[u + 2] = *(const float*)(pb + (uint64_t)id.z * rowb);
+                v[u + 3] = *(const float*)(pb + (uint64_t)id.w * rowb);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s = s + v[u];
+            k += 8;
+        }
+        for (; k < K; ++k) s = s + *(const float*)(pb + (uint64_t)lst[k] * rowb);
         S.sums[q][cl] = s;
         const size_t pix = (size_t)(r0 + qr) * W + c0 + qc;
         f.out_prob[pix * C + cl] = s / (float)K;
