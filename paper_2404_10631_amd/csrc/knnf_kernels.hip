@@ -215,6 +215,17 @@ __device__ __forceinline__ uint64_t lanex64(uint64_t v) {
     return ((uint64_t)lanex<X>((uint32_t)(v >> 32)) << 32) | (uint64_t)lanex<X>((uint32_t)v);
 }
 
+// The u32 network sorts bit patterns of non-negative binary32 values (pass-A
+// distances, +inf padding): their unsigned order is their numeric order, so
+// a cross-lane pair keeps max(x, p) or min(x, p) as the median of x, p and
+// +inf or -inf (one v_med3_f32).
+__device__ __forceinline__ float side_sel(bool upper) {
+    return __int_as_float(upper ? 0x7f800000 : (int)0xff800000u);
+}
+__device__ __forceinline__ uint32_t keep_side(uint32_t x, uint32_t p, float sel) {
+    return __float_as_uint(__builtin_amdgcn_fmed3f(__uint_as_float(x), __uint_as_float(p), sel));
+}
+
 template <int E, int KS>
 __device__ __forceinline__ void seg_mirror_u32(uint32_t (&x)[E], int lp) {
     if constexpr (KS <= E) {
@@ -227,12 +238,12 @@ __device__ __forceinline__ void seg_mirror_u32(uint32_t (&x)[E], int lp) {
             x[r ^ M] = max(a, b);
         }
     } else {
-        const bool upper = (lp & (KS / (2 * E))) != 0;
+        const float sel = side_sel((lp & (KS / (2 * E))) != 0);
         uint32_t p[E];
 #pragma unroll
         for (int r = 0; r < E; ++r) p[r] = lanex<KS / E - 1>(x[E - 1 - r]);
 #pragma unroll
-        for (int r = 0; r < E; ++r) x[r] = upper ? max(x[r], p[r]) : min(x[r], p[r]);
+        for (int r = 0; r < E; ++r) x[r] = keep_side(x[r], p[r], sel);
     }
 }
 
@@ -247,12 +258,9 @@ __device__ __forceinline__ void seg_half_u32(uint32_t (&x)[E], int lp) {
             x[r | D] = max(a, b);
         }
     } else {
-        const bool upper = (lp & (D / E)) != 0;
+        const float sel = side_sel((lp & (D / E)) != 0);
 #pragma unroll
-        for (int r = 0; r < E; ++r) {
-            const uint32_t p = lanex<D / E>(x[r]);
-            x[r] = upper ? max(x[r], p) : min(x[r], p);
-        }
+        for (int r = 0; r < E; ++r) x[r] = keep_side(x[r], lanex<D / E>(x[r]), sel);
     }
 }
 
@@ -634,15 +642,10 @@ __device__ __forceinline__ void process_tile(TileState<QR, QC>& S, const FrameDe
     const float qnan = __int_as_float(0x7fc00000);
     const float pinf = __int_as_float(0x7f800000);
 
-    // ---- query values
     if (L < Q) {
-        const int qr = L / QC, qc = L % QC;
-        const bool ok = qr < nqr && qc < nqc;
-        S.iq[L] = ok ? pc1[(size_t)(r0 + qr) * W + c0 + qc] : qnan;
         S.listn[L] = 0;
         S.tau[L] = 0ull;
     }
-    wave_sync();
 
     // ---- pass A.  The K-th smallest distance d_K of a compact block bounds
     // the query's final K-th key from above by (d_K, max index).  All Q
@@ -662,22 +665,33 @@ __device__ __forceinline__ void process_tile(TileState<QR, QC>& S, const FrameDe
         const int bc = 1 << lbc;
         const int rb = min(max(r - br / 2, i0w), i1w - br + 1);
         const int cb = max(0, min(c - bc / 2, W - bc));
-        const float iqs = S.iq[sq];
+        // I of the segment's query pixel (NaN for pixels off the frame)
+        const float iqs = sok ? pc1[(uint32_t)r * (uint32_t)W + (uint32_t)c] : qnan;
         const float frq = feat(lam, r), fcq = feat(lam, c);
+        // every lane loads (columns past the edge clamped: rows rb .. rb+br-1
+        // are inside the frame even for queries off its bottom edge), so all
+        // E loads are in flight together
+        float pv[E];
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            const int e = lp * E + u;
+            const int i = rb + (e >> lbc);
+            const int j = min(cb + (e & (bc - 1)), W - 1);
+            pv[u] = pc1[(uint32_t)i * (uint32_t)W + (uint32_t)j];
+        }
         uint32_t x[E];
 #pragma unroll
         for (int u = 0; u < E; ++u) {
             const int e = lp * E + u;
             const int i = rb + (e >> lbc);
             const int j = cb + (e & (bc - 1));
-            x[u] = 0xffffffffu;
-            if (sok && j < W) {
-                const float a = frq - feat(lam, i);
-                const float b = fcq - feat(lam, j);
-                const float ee = iqs - pc1[(size_t)i * W + j];
-                x[u] = __float_as_uint(fmaf(ee, ee, fmaf(b, b, a * a)));
-            }
+            const float a = frq - feat(lam, i);
+            const float b = fcq - feat(lam, j);
+            const float ee = iqs - pv[u];
+            const uint32_t d = __float_as_uint(fmaf(ee, ee, fmaf(b, b, a * a)));
+            x[u] = (sok && j < W) ? d : 0x7f800000u;  // +inf: no candidate
         }
+        if (lp == 0) S.iq[sq] = iqs;
         seg_sort_u32<E>(x, lp);
 #pragma unroll
         for (int u = 0; u < E; ++u) S.list[sq][lp * E + u] = x[u];
