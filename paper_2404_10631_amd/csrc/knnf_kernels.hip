@@ -671,25 +671,52 @@ __device__ __forceinline__ void process_tile(TileState<QR, QC>& S, const FrameDe
         // every lane loads (columns past the edge clamped: rows rb .. rb+br-1
         // are inside the frame even for queries off its bottom edge), so all
         // E loads are in flight together
-        float pv[E];
-#pragma unroll
-        for (int u = 0; u < E; ++u) {
-            const int e = lp * E + u;
-            const int i = rb + (e >> lbc);
-            const int j = min(cb + (e & (bc - 1)), W - 1);
-            pv[u] = pc1[(uint32_t)i * (uint32_t)W + (uint32_t)j];
-        }
         uint32_t x[E];
+        if constexpr (E <= 8) {
+            // blocks are at least 8 columns wide, so a lane's E elements lie
+            // in one row, at consecutive columns
+            const int e0 = lp * E;
+            const int ib = rb + (e0 >> lbc);
+            const int jb = cb + (e0 & (bc - 1));
+            const float* __restrict__ rowp = pc1 + (size_t)(uint32_t)ib * (uint32_t)W;
+            float pv[E];
+            if (W >= WAVE) {
 #pragma unroll
-        for (int u = 0; u < E; ++u) {
-            const int e = lp * E + u;
-            const int i = rb + (e >> lbc);
-            const int j = cb + (e & (bc - 1));
-            const float a = frq - feat(lam, i);
-            const float b = fcq - feat(lam, j);
-            const float ee = iqs - pv[u];
-            const uint32_t d = __float_as_uint(fmaf(ee, ee, fmaf(b, b, a * a)));
-            x[u] = (sok && j < W) ? d : 0x7f800000u;  // +inf: no candidate
+                for (int u = 0; u < E; ++u) pv[u] = rowp[jb + u];
+            } else {
+#pragma unroll
+                for (int u = 0; u < E; ++u) pv[u] = rowp[min(jb + u, W - 1)];
+            }
+            const float a = frq - feat(lam, ib);
+            const float a2 = a * a;
+#pragma unroll
+            for (int u = 0; u < E; ++u) {
+                const int j = jb + u;
+                const float b = fcq - feat(lam, j);
+                const float ee = iqs - pv[u];
+                const uint32_t d = __float_as_uint(fmaf(ee, ee, fmaf(b, b, a2)));
+                x[u] = (sok && j < W) ? d : 0x7f800000u;  // +inf: no candidate
+            }
+        } else {
+            float pv[E];
+#pragma unroll
+            for (int u = 0; u < E; ++u) {
+                const int e = lp * E + u;
+                const int i = rb + (e >> lbc);
+                const int j = min(cb + (e & (bc - 1)), W - 1);
+                pv[u] = pc1[(uint32_t)i * (uint32_t)W + (uint32_t)j];
+            }
+#pragma unroll
+            for (int u = 0; u < E; ++u) {
+                const int e = lp * E + u;
+                const int i = rb + (e >> lbc);
+                const int j = cb + (e & (bc - 1));
+                const float a = frq - feat(lam, i);
+                const float b = fcq - feat(lam, j);
+                const float ee = iqs - pv[u];
+                const uint32_t d = __float_as_uint(fmaf(ee, ee, fmaf(b, b, a * a)));
+                x[u] = (sok && j < W) ? d : 0x7f800000u;  // +inf: no candidate
+            }
         }
         if (lp == 0) S.iq[sq] = iqs;
         seg_sort_u32<E>(x, lp);
@@ -912,24 +939,72 @@ __device__ __forceinline__ void process_tile(TileState<QR, QC>& S, const FrameDe
     }
     wave_sync();
     {
-        // all other queries: one segmented sort of their candidate buffers
+        // all other queries: one segmented sort of their candidate buffers.
+        // The network sorts 32-bit packed keys: the distance bits (clamped
+        // below +inf) with their 6 low bits replaced by the buffer slot.
+        // Packed order is exact wherever the distance parts differ; runs of
+        // equal distance parts are then put in (d, idx) order on the full
+        // keys by odd-even transposition (rarely needed).
         const int cq = S.cnt[sq];
         const bool own = sok && S.listn[sq] == 0;
-        uint64_t x[E];
+        uint32_t x[E];
 #pragma unroll
         for (int u = 0; u < E; ++u) {
-            const int e = lp * E + u;
-            x[u] = (own && e < cq) ? S.pend[sq][e] : KEY_INF;
+            // slot assignment rotated by segment: one read touches every bank
+            const int e = ((u + sq) % E) * P + lp;
+            const uint32_t dh = (uint32_t)(S.pend[sq][e] >> 32);
+            x[u] = (own && e < cq) ? ((min(dh, 0x7f7fffc0u) & ~63u) | (uint32_t)e) : 0x7f800000u;
         }
-        seg_sort_key<E>(x, lp);
+        seg_sort_u32<E>(x, lp);
+        uint64_t y[E];
+#pragma unroll
+        for (int u = 0; u < E; ++u) y[u] = x[u] < 0x7f800000u ? S.pend[sq][x[u] & 63u] : KEY_INF;
+        // neighbours in sorted order: element lp*E + u, the next one is u + 1
+        // or the next lane's element 0 (same segment while lp < P - 1)
+        bool tie = false;
+#pragma unroll
+        for (int u = 0; u + 1 < E; ++u) tie |= (x[u] >> 6) == (x[u + 1] >> 6) && x[u] < 0x7f800000u;
+        {
+            const uint32_t nx = (uint32_t)__builtin_amdgcn_mov_dpp((int)x[0], 0x101, 0xF, 0xF, false);  // row_shl:1
+            tie |= lp < P - 1 && (x[E - 1] >> 6) == (nx >> 6) && x[E - 1] < 0x7f800000u;
+        }
+        if (ballot(tie)) {
+            for (;;) {
+                bool sw = false;
+#pragma unroll
+                for (int ph = 0; ph < 2; ++ph) {
+#pragma unroll
+                    for (int u = ph; u + 1 < E; u += 2) {
+                        const uint64_t a = y[u], b = y[u + 1];
+                        const bool t = b < a;
+                        y[u] = t ? b : a;
+                        y[u + 1] = t ? a : b;
+                        sw |= t;
+                    }
+                    if ((ph == 1) == ((E & 1) == 0)) {
+                        // pair (lane's last, next lane's first)
+                        const uint64_t nx = (uint64_t)(uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)y[0], 0x101, 0xF, 0xF, false) |
+                                            ((uint64_t)(uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(y[0] >> 32), 0x101, 0xF, 0xF, false) << 32);
+                        const uint64_t pv = (uint64_t)(uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)y[E - 1], 0x111, 0xF, 0xF, false) |
+                                            ((uint64_t)(uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(y[E - 1] >> 32), 0x111, 0xF, 0xF, false) << 32);
+                        const bool tn = lp < P - 1 && nx < y[E - 1];  // this lane keeps the smaller
+                        const bool tp = lp > 0 && y[0] < pv;          // this lane keeps the larger
+                        y[E - 1] = tn ? nx : y[E - 1];
+                        y[0] = tp ? pv : y[0];
+                        sw |= tn;
+                    }
+                }
+                if (!ballot(sw)) break;
+            }
+        }
         const size_t pix = (size_t)(r0 + sqr) * W + c0 + sqc;
 #pragma unroll
         for (int u = 0; u < E; ++u) {
             const int e = lp * E + u;
             if (own && e < K) {
-                S.list[sq][e] = (uint32_t)x[u];
-                if (f.out_nbr) f.out_nbr[pix * K + e] = (int32_t)(uint32_t)x[u];
-                if (f.out_dist) f.out_dist[pix * K + e] = __uint_as_float((uint32_t)(x[u] >> 32));
+                S.list[sq][e] = (uint32_t)y[u];
+                if (f.out_nbr) f.out_nbr[pix * K + e] = (int32_t)(uint32_t)y[u];
+                if (f.out_dist) f.out_dist[pix * K + e] = __uint_as_float((uint32_t)(y[u] >> 32));
             }
         }
     }
