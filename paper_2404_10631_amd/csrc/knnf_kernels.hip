@@ -356,17 +356,27 @@ __device__ __forceinline__ void seg_sort_key(uint64_t (&x)[E], int lp) {
 template <int QR, int QC>
 struct alignas(16) TileState {
     static constexpr int Q = QR * QC;
-    uint64_t pend[Q][WAVE];   // keys of candidates that passed the bound, unsorted
+    union {
+        uint64_t pend[Q][WAVE];  // keys of candidates that passed the bound, unsorted
+        float sums[Q][MAXC];     // class sums for the argmax (after the final selection)
+    };
     uint32_t list[Q][WAVE];   // sorted top-K linear indices (first listn valid);
                               // before the scan: pass-A block distances
-    float sums[Q][MAXC];      // class sums for the argmax
-    uint64_t tau[Q];          // current bound on the K-th key of each query
-    uint32_t tauhi[Q];        // its distance bits (high word)
-    float a2t[A2ROWS + A2PAD][QR];  // fl32(a*a) for a block of window rows (+inf: inactive)
+    uint32_t tauhi[Q];        // distance bits of the current bound on the K-th key
     float iq[Q];              // I of each query pixel (NaN for pixels off the frame)
     int listn[Q];             // valid list entries (<= K)
     int cnt[Q];               // pending entries (mirror of the scan's registers)
 };
+
+// The exhaustive scan also keeps the full bound key (index included after a
+// merge) and a table of row terms; the pruned scan needs neither.
+template <int QR, int QC, bool PRUNE>
+struct alignas(16) TileLds : TileState<QR, QC> {
+    uint64_t tau[QR * QC];          // current bound on the K-th key of each query
+    float a2t[A2ROWS + A2PAD][QR];  // fl32(a*a) for a block of window rows (+inf: inactive)
+};
+template <int QR, int QC>
+struct alignas(16) TileLds<QR, QC, true> : TileState<QR, QC> {};
 
 // Coordinate feature fr(x) = fl32(lambda * (float)x).
 __device__ __forceinline__ float feat(float lam, int x) { return lam * (float)x; }
@@ -631,7 +641,7 @@ __device__ __forceinline__ bool block_cand(const FrameDesc& f, int r, int c, int
 
 // Process one tile: query pixels (r0 + qr, c0 + qc), qr < QR, qc < QC.
 template <int QR, int QC, bool PRUNE>
-__device__ __forceinline__ void process_tile(TileState<QR, QC>& S, const FrameDesc& f, int r0,
+__device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const FrameDesc& f, int r0,
                                              int c0) {
     constexpr int Q = QR * QC;
     const int L = lane_id();
@@ -642,10 +652,7 @@ __device__ __forceinline__ void process_tile(TileState<QR, QC>& S, const FrameDe
     const float qnan = __int_as_float(0x7fc00000);
     const float pinf = __int_as_float(0x7f800000);
 
-    if (L < Q) {
-        S.listn[L] = 0;
-        S.tau[L] = 0ull;
-    }
+    if (L < Q) S.listn[L] = 0;
 
     // ---- pass A.  The K-th smallest distance d_K of a compact block bounds
     // the query's final K-th key from above by (d_K, max index).  All Q
@@ -726,7 +733,7 @@ __device__ __forceinline__ void process_tile(TileState<QR, QC>& S, const FrameDe
         if (L < Q) {
             const bool ok = (L / QC) < nqr && (L % QC) < nqc;
             const uint32_t dk = S.list[L][K - 1];
-            S.tau[L] = ok ? (((uint64_t)dk << 32) | 0xffffffffull) : 0ull;
+            if constexpr (!PRUNE) S.tau[L] = ok ? (((uint64_t)dk << 32) | 0xffffffffull) : 0ull;
             S.tauhi[L] = ok ? dk : 0u;
         }
         wave_sync();
@@ -1085,7 +1092,7 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 
 template <int QR, int QC, int WPB, bool PRUNE>
 __global__ void __launch_bounds__(WPB * WAVE) filter_frame_kernel(FrameDesc f) {
-    __shared__ TileState<QR, QC> lds[WPB];
+    __shared__ TileLds<QR, QC, PRUNE> lds[WPB];
     const int w = uni((int)(threadIdx.x >> 6));
     const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
     const int ntc = (f.W + QC - 1) / QC;
@@ -1109,7 +1116,7 @@ __global__ void __launch_bounds__(WPB * WAVE)
 filter_batch_kernel(const FrameDesc* __restrict__ frames, const uint32_t* __restrict__ task_start,
                     const uint32_t* __restrict__ tile_base, uint32_t nframes, uint32_t total_tasks,
                     uint32_t claim, uint32_t* counter) {
-    __shared__ TileState<QR, QC> lds[WPB];
+    __shared__ TileLds<QR, QC, PRUNE> lds[WPB];
     const int w = uni((int)(threadIdx.x >> 6));
     const int L = lane_id();
     for (;;) {
@@ -1148,7 +1155,7 @@ __global__ void __launch_bounds__(WPB * WAVE)
 filter_items_kernel(const FrameDesc* __restrict__ frames, const uint32_t* __restrict__ task_start,
                     const uint32_t* __restrict__ tile_base, uint32_t nframes,
                     uint32_t total_tasks) {
-    __shared__ TileState<QR, QC> lds[WPB];
+    __shared__ TileLds<QR, QC, PRUNE> lds[WPB];
     const int w = uni((int)(threadIdx.x >> 6));
     const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
     const uint64_t t64 = (uint64_t)b * WPB + w;
