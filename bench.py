@@ -117,7 +117,8 @@ def batch_leg(ctx, plan, stream, reps=3):
 P99_TARGET_MS = 10.0   # pre-registered per-frame latency target of the served stream
 
 
-def serve_leg(ctx, plan, n_frames, rate, sweep=(1000.0, 2000.0, 4000.0, 5000.0, 6000.0, 7000.0, 8000.0),
+def serve_leg(ctx, plan, n_frames, rate,
+              sweep=(1000.0, 2000.0, 4000.0, 6000.0, 8000.0, 10000.0, 12000.0, 16000.0),
               sweep_frames=800):
     """Poisson stream of mixed frame sizes: continuous-batching server vs plain
     one-frame-at-a-time launches, both fed by the same arrival schedules."""

@@ -423,7 +423,10 @@ __device__ __forceinline__ uint64_t flush_query(TileState<QR, QC>& S, const Fram
     if (L >= K) key = KEY_INF;
     const int nl = min(K, listn + cnt);
     wave_sync();
-    if (L < K) S.list[q][L] = (uint32_t)key;
+    // a slot without a candidate (only with non-finite inputs, or inputs that
+    // change during the launch) gathers the query pixel's own row, never an
+    // address outside the frame
+    if (L < K) S.list[q][L] = (final && key == KEY_INF) ? (uint32_t)(r * W + c) : (uint32_t)key;
     if (final && L < K) {
         const size_t pix = (size_t)r * W + c;
         if (f.out_nbr) f.out_nbr[pix * K + L] = (int32_t)(uint32_t)key;
@@ -1009,7 +1012,8 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
         for (int u = 0; u < E; ++u) {
             const int e = lp * E + u;
             if (own && e < K) {
-                S.list[sq][e] = (uint32_t)y[u];
+                // a slot without a candidate gathers the query's own row (see flush_query)
+                S.list[sq][e] = y[u] == KEY_INF ? (uint32_t)pix : (uint32_t)y[u];
                 if (f.out_nbr) f.out_nbr[pix * K + e] = (int32_t)(uint32_t)y[u];
                 if (f.out_dist) f.out_dist[pix * K + e] = __uint_as_float((uint32_t)(y[u] >> 32));
             }

@@ -87,7 +87,7 @@ struct Job {
     knnf_frame dev{};
     uint32_t ntiles = 0, next_tile = 0;
     int outstanding = 0;          // launched steps holding tiles of this job
-    bool waited = false;          // compute streams were told to wait for its copy
+    uint32_t waited = 0;          // compute streams (bit per step slot) told to wait for its copy
     hipEvent_t copied = nullptr;  // inputs are in the pool
     double t_arrival = 0, t_admit = 0, t_launch = -1, t_done = 0;
 };
@@ -238,9 +238,12 @@ bool launch_step(knnf_server* s) {
         Job& j = s->jobs[s->ready.front()];
         const uint32_t left = j.ntiles - j.next_tile;
         const uint32_t take = (uint32_t)std::min<uint64_t>(left, budget);
-        if (!j.waited) {
+        // a frame split over several steps may run on several streams: each
+        // of them waits for the copy of its inputs before its first tile
+        const uint32_t sbit = 1u << (uint32_t)(st - s->steps.data());
+        if (!(j.waited & sbit)) {
             if (hipStreamWaitEvent(st->stream, j.copied, 0) != hipSuccess) s->sticky = KNNF_EDEVICE;
-            j.waited = true;
+            j.waited |= sbit;
         }
         knnf::WorkItem w;
         w.f = knnf::desc_of(j.dev);
@@ -256,7 +259,9 @@ bool launch_step(knnf_server* s) {
         if (plain) break;
     }
     knnf_status rc;
-    if (plain) {
+    if (plain || (items.size() == 1 && items[0].tile0 == 0 &&
+                  items[0].ntiles == s->jobs[st->tickets[0]].ntiles)) {
+        // one whole frame: the single-frame launch (no work table to copy)
         rc = knnf_filter(s->ctx, &s->jobs[st->tickets[0]].dev, &s->plan, st->stream);
     } else {
         rc = knnf::launch_items(s->ctx, items.data(), (int)items.size(), s->plan, st->stream);

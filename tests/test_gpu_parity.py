@@ -22,6 +22,10 @@ PROB_TOL = 1e-6
 SHAPES = [(1, 8), (1, 16), (2, 4), (2, 8), (4, 4)]
 EXH8 = dict(search=0, tile_rows=2, tile_cols=8, waves=2)
 PRU8 = dict(search=1, tile_rows=2, tile_cols=8, waves=2)
+# the default plan and the other 8-query shape
+PRU24 = dict(search=1, tile_rows=2, tile_cols=4, waves=1)
+PRU18 = dict(search=1, tile_rows=1, tile_cols=8, waves=1)
+TIE_PLANS = (EXH8, PRU8, PRU24, PRU18)
 ALL_PLANS = [dict(search=s, tile_rows=r, tile_cols=c, waves=w)
              for s in (0, 1) for (r, c) in SHAPES for w in (1, 2, 4)]
 
@@ -112,7 +116,7 @@ def test_ties_constant_band_lambda_zero(ctx):
     pc1 = np.full((H, W), 0.5, np.float32)
     _, prob = inputs.g_unif(H, W, 4)
     ref = oracle.knn_filter(pc1, prob, K, R, 0.0)
-    for plan in (EXH8, PRU8):
+    for plan in TIE_PLANS:
         say(f"constant band lambda 0 plan={plan}")
         assert_parity(run_gpu(ctx, pc1, prob, K, R, 0.0, plan), ref, "const-l0")
 
@@ -123,9 +127,24 @@ def test_ties_dyadic(ctx):
     pc1 = (rng.integers(0, 5, size=(H, W)) / 4.0).astype(np.float32)
     _, prob = inputs.g_unif(H, W, 5)
     ref = oracle.knn_filter(pc1, prob, K, R, 0.25)
-    for plan in (EXH8, PRU8):
+    for plan in TIE_PLANS:
         say(f"dyadic ties plan={plan}")
         assert_parity(run_gpu(ctx, pc1, prob, K, R, 0.25, plan), ref, "dyadic")
+
+
+def test_near_ties_low_bits(ctx):
+    """Distances that differ only in their last mantissa bits: a fifth of the
+    pixels sit near 0, the rest near 1 (offsets below 1e-5), lambda = 0, and K
+    reaches into the near-1 group, whose order is decided by those bits."""
+    rng = np.random.default_rng(21)
+    H, W, K, R = 24, 40, 60, 2
+    low = rng.random((H, W)) < 0.2
+    pc1 = (np.where(low, 0.0, 1.0) + rng.random((H, W)) * 1e-5).astype(np.float32)
+    _, prob = inputs.g_unif(H, W, 6)
+    ref = oracle.knn_filter(pc1, prob, K, R, 0.0)
+    for plan in TIE_PLANS:
+        say(f"near ties plan={plan}")
+        assert_parity(run_gpu(ctx, pc1, prob, K, R, 0.0, plan), ref, "near-ties")
 
 
 @pytest.mark.parametrize("C", [1, 3, 16])

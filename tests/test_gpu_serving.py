@@ -67,6 +67,26 @@ def test_served_mix_equals_alone(ctx, mode):
         assert np.max(np.abs(results[k][0] - ro)) <= 1e-6
 
 
+def test_split_frames_wait_for_their_inputs(ctx):
+    """Frames split over many small steps run on both compute streams; every
+    step waits for the copy of its frame's inputs, so the results equal the
+    frames filtered alone (regression: only the first step of a frame used
+    to wait, so later steps on the other stream could read inputs still
+    being copied)."""
+    specs = [inputs.FrameSpec("derma", 400, 420, 11 + k, K=40, R=14) for k in range(3)]
+    data = [s.make() for s in specs]
+    frames = [HostFrame(p, q, s.K, s.R, s.lam) for s, (p, q) in zip(specs, data)]
+    say("split frames over small steps")
+    with Server(ctx, 256 << 20, max_inflight=2, step_tiles=512) as srv:
+        results = {}
+        replay(srv, frames, [0.0] * len(frames),
+               keep=lambda k, v: results.__setitem__(k, srv.view_arrays(v)))
+    for k, (s, d) in enumerate(zip(specs, data)):
+        alone = _alone(ctx, s, d)
+        assert np.array_equal(results[k][1], alone[1]), f"class differs for frame {k}"
+        assert np.array_equal(results[k][0], alone[0]), f"prob differs for frame {k}"
+
+
 def test_tiny_pool_admits_as_memory_frees(ctx):
     """A pool that holds one large frame at a time still serves a burst."""
     spec = inputs.FrameSpec("brain", 200, 200, 9, K=40, R=14)
