@@ -225,7 +225,8 @@ typedef struct {
     int32_t mode;          /* knnf_serve_mode                                   */
     int32_t max_queue;     /* frames submitted but not admitted; 0: 4096         */
     int32_t max_inflight;  /* GPU steps queued at once (batched mode), 0: 2; <=4 */
-    int32_t step_tiles;    /* tile budget of one batched step; 0: 32768          */
+    int32_t step_tiles;    /* tile budget of one batched step; 0: 32768 (a lone  */
+                           /* frame with nothing waiting runs whole)             */
     knnf_plan plan;        /* kernel plan; zero fields: the context's default,    */
                            /* except launch, which defaults to KNNF_LAUNCH_GRID   */
 } knnf_server_opts;

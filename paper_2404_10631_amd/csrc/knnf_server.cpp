@@ -7,8 +7,10 @@
 //      a copy stream;
 //   2. builds GPU steps: one batched launch over tile ranges of all admitted
 //      frames in arrival order, up to a tile budget, so a large frame is
-//      processed in slices and later arrivals join the next step; up to
-//      `max_inflight` steps are queued on separate compute streams;
+//      processed in slices and later arrivals join the next step (a lone
+//      frame with nothing waiting runs whole); up to `max_inflight` steps are
+//      queued on separate compute streams, each waiting for the input copy of
+//      every frame it touches;
 //   3. watches step completion events and marks a frame done when the last
 //      step holding its tiles has finished.
 // In plain mode each step is one whole frame, launched alone (the baseline).
@@ -234,6 +236,10 @@ bool launch_step(knnf_server* s) {
     const bool plain = s->opts.mode == KNNF_SERVE_PLAIN;
     std::vector<knnf::WorkItem> items;
     uint64_t budget = plain ? ~0ull : (uint64_t)s->opts.step_tiles;
+    // an idle server (one frame ready, nothing waiting for admission) runs it
+    // whole: slicing only helps frames that arrive behind it, and those still
+    // start at once on the other stream
+    if (s->ready.size() == 1 && s->queue.empty()) budget = ~0ull;
     while (!s->ready.empty() && budget > 0) {
         Job& j = s->jobs[s->ready.front()];
         const uint32_t left = j.ntiles - j.next_tile;

@@ -99,6 +99,55 @@ def g_derma(H: int, W: int, seed: int, C: int = NUM_CLASSES):
 GENERATORS = {"unif": g_unif, "brain": g_brain, "derma": g_derma}
 
 
+def g_cube(H: int, W: int, B: int, seed: int, kind: str = "brain"):
+    """A hyperspectral cube for the PC1 projection step, with the band
+    averages and the first eigenvector it is given (the covariance and Jacobi
+    steps are not part of the library).
+
+    Regions as in ``g_brain`` (six Voronoi cells) or ``g_derma`` (lesion and
+    skin); every region has a smooth reflectance spectrum in [0, 1] (a base
+    curve plus two Gaussian bumps over the bands), scaled by a smooth
+    illumination field, plus N(0, 0.01) noise.  ``mean`` is the base curve and
+    ``vec`` the unit direction from the base curve to the first region's
+    spectrum -- generator parameters, not statistics of the cube.
+
+    Returns ``cube`` float32 [H*W, B] (pixel-major, bands contiguous),
+    ``mean`` and ``vec`` float64 [B].
+    """
+    rng = np.random.default_rng(seed)
+    bands = np.linspace(0.0, 1.0, B)
+    base = 0.35 + 0.15 * np.sin(2.0 * np.pi * (bands * rng.uniform(0.6, 1.4) + rng.uniform(0, 1)))
+    yy, xx = np.meshgrid(np.arange(H, dtype=np.float64), np.arange(W, dtype=np.float64),
+                         indexing="ij")
+    if kind == "brain":
+        sites = 6
+        sy = rng.uniform(0.0, H, size=sites)
+        sx = rng.uniform(0.0, W, size=sites)
+        d2 = (yy[None] - sy[:, None, None]) ** 2 + (xx[None] - sx[:, None, None]) ** 2
+        label = np.argmin(d2, axis=0)
+    elif kind == "derma":
+        sites = 2
+        cy, cx = H / 2.0 + rng.uniform(-0.15, 0.15) * H, W / 2.0 + rng.uniform(-0.15, 0.15) * W
+        ay, ax = rng.uniform(0.2, 0.35) * H, rng.uniform(0.2, 0.35) * W
+        label = (((yy - cy) / ay) ** 2 + ((xx - cx) / ax) ** 2 > 1.0).astype(np.int64)
+    else:
+        raise ValueError(f"unknown cube kind {kind!r}")
+    spectra = np.empty((sites, B))
+    for k in range(sites):
+        bump = np.zeros(B)
+        for _ in range(2):
+            c, w, a = rng.uniform(0.1, 0.9), rng.uniform(0.05, 0.2), rng.uniform(-0.25, 0.25)
+            bump += a * np.exp(-0.5 * ((bands - c) / w) ** 2)
+        spectra[k] = np.clip(base + bump, 0.0, 1.0)
+    illum = 1.0 + 0.1 * np.sin(yy / max(H, 1) * rng.uniform(2, 6) + rng.uniform(0, 6)) \
+        * np.cos(xx / max(W, 1) * rng.uniform(2, 6))
+    cube = spectra[label] * illum[..., None] + rng.normal(0.0, 0.01, size=(H, W, B))
+    direction = spectra[0] - base
+    vec = direction / np.sqrt(np.sum(direction * direction))
+    return (np.ascontiguousarray(cube.reshape(H * W, B).astype(np.float32)),
+            np.ascontiguousarray(base), np.ascontiguousarray(vec))
+
+
 @dataclass(frozen=True)
 class FrameSpec:
     """One frame of a workload: generator, shape, seed and filter parameters."""
