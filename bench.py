@@ -30,6 +30,7 @@ if ROOT not in sys.path:
 
 METRIC = "filtered pixels/sec at K=40 (served vs plain); p50/p99 frame latency"
 PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X published FP32 vector peak (256 CU, 2.4 GHz)
+PEAK_HBM_GBS = 8000.0             # MI355X published HBM3E bandwidth
 FLOP_PER_PAIR = 8                 # 3 subtractions, 3 squares, 2 additions of Eq. 1
 
 
@@ -45,9 +46,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
-    ap.add_argument("--legs", default="plain,batch,serve",
+    ap.add_argument("--legs", default="plain,batch,serve,pc1",
                     help="comma list of: plain (headline), batch (uneven / small-frame "
-                         "batches), serve (Poisson mixed stream)")
+                         "batches), serve (Poisson mixed stream), pc1 (the projection "
+                         "step that produces the band)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (to scale HBM counters)")
     ap.add_argument("--serve-frames", type=int, default=2000)
@@ -86,6 +88,45 @@ def time_gpu(fn, reps):
         fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / reps
+
+
+def pc1_leg(ctx, stream, reps=20):
+    """PC1 projection of a brain-like cube (W480 x H380, 128 bands) on the
+    device: centre, project, min-max normalise (two launches), HBM-bound."""
+    import torch
+
+    from paper_2404_10631_amd import _lib, inputs
+
+    H, W, B = 380, 480, 128
+    cube, mean, vec = inputs.g_cube(H, W, B, 1)
+    dcube = torch.from_numpy(cube).cuda()
+    dmean = torch.from_numpy(mean).cuda()
+    dvec = torch.from_numpy(vec).cuda()
+    out = torch.empty(H * W, dtype=torch.float32, device="cuda")
+    npix = H * W
+
+    def run():
+        _lib.knnf_pc1(ctx, dcube.data_ptr(), npix, B, dmean.data_ptr(), dvec.data_ptr(),
+                      out.data_ptr(), True, stream)
+
+    run()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()  # on torch's current stream, the one the launches use
+    for _ in range(reps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    # algorithmic bytes: the cube once, the binary64 projection written and
+    # read back for the normalisation, the binary32 band written
+    nbytes = npix * B * 4 + npix * 8 * 2 + npix * 4 + B * 16
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"workload": f"brain-like cube W{W}xH{H}, {B} bands, normalised", "ms": round(ms, 5),
+            "pixels_per_s": round(npix / (ms * 1e-3), 1), "bytes": nbytes,
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                         "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4)}}
 
 
 def batch_leg(ctx, plan, stream, reps=3):
@@ -290,6 +331,9 @@ def main():
     if "serve" in legs:
         print("bench: serve leg", file=sys.stderr, flush=True)
         out["serving"] = serve_leg(ctx, plan, args.serve_frames, args.serve_rate)
+    if "pc1" in legs:
+        print("bench: pc1 leg", file=sys.stderr, flush=True)
+        out["pc1_projection"] = pc1_leg(ctx, stream)
     if not args.no_cpu:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(spec, pc1, prob, args.cpu_seconds)

@@ -286,6 +286,38 @@ knnf_status knnf_server_drain(knnf_server* srv, double timeout_s);
 /* Stop the scheduler after the GPU work in flight ends, and free the server. */
 knnf_status knnf_server_destroy(knnf_server* srv);
 
+/* ---- PC1 projection: the one-band image the filter reads ---------------
+ *
+ * The PCA of Sec. II.C.2 centres every band by its average (step (i)) and
+ * projects the centred image onto the first eigenvector of the covariance
+ * matrix, keeping that one component (step (iv)); the GPU versions do both
+ * in double precision (Sec. III.A.2.a/d, Sec. III.B.2.a/d).  The covariance
+ * and eigenvector steps (ii)-(iii) are not part of this library: the band
+ * averages and the eigenvector are inputs.  The filter reads a normalised I
+ * (Sec. II.C.3); normalisation here is min-max to [0, 1] over the frame.
+ *
+ *   I[p]  = sum_b (cube[p][b] - mean[b]) * vec[b]        binary64
+ *   I'[p] = (I[p] - min I) / (max I - min I)             binary64, 0 if I is constant
+ *   out[p] = I'[p] (normalize != 0) or I[p], rounded once to binary32
+ *
+ * cube  device, npix x bands float32, pixel-major (a pixel's bands contiguous)
+ * mean  device, bands float64 (band averages)
+ * vec   device, bands float64 (first eigenvector)
+ * out   device, npix float32; may be the pc1 buffer of a knnf_frame
+ * Asynchronous on `stream`.  Uses a context workspace (8 B per pixel when
+ * normalize != 0, plus 16 KB) that grows on first use of a larger frame (that
+ * call synchronizes the device and allocates).  Calls that overlap on one
+ * context race on the workspace: issue them on one stream.
+ * Errors: KNNF_EINVAL for a NULL argument, npix outside [1, 2^40], bands
+ * outside [1, KNNF_PC1_MAX_BANDS]; KNNF_ENOMEM if the workspace cannot grow;
+ * KNNF_EDEVICE for a failed launch.
+ */
+#define KNNF_PC1_MAX_BANDS 4096
+#define KNNF_PC1_MAX_PIXELS (1LL << 40)
+knnf_status knnf_pc1(knnf_ctx* ctx, const float* cube, int64_t npix, int32_t bands,
+                     const double* mean, const double* vec, float* out, int32_t normalize,
+                     void* stream);
+
 /* Text of the last error on the calling thread ("" if none). */
 const char* knnf_last_error(void);
 

@@ -124,6 +124,7 @@ _SIGS = {
     "knnf_server_drain": (_I, [_P, ctypes.c_double]),
     "knnf_server_destroy": (_I, [_P]),
     "knnf_version": (ctypes.c_char_p, []),
+    "knnf_pc1": (_I, [_P, _P, ctypes.c_int64, ctypes.c_int32, _P, _P, _P, ctypes.c_int32, _P]),
 }
 
 _lib = None
@@ -267,3 +268,10 @@ def knnf_server_drain(srv: int, timeout_s: float = 0.0) -> None:
 
 def knnf_server_destroy(srv: int) -> None:
     check(load().knnf_server_destroy(srv))
+
+
+def knnf_pc1(ctx: int, cube_ptr: int, npix: int, bands: int, mean_ptr: int, vec_ptr: int,
+             out_ptr: int, normalize: bool = True, stream: int = 0) -> None:
+    """PC1 projection of a device cube (see include/knnf.h); device pointers."""
+    check(load().knnf_pc1(ctx, cube_ptr, int(npix), int(bands), mean_ptr, vec_ptr, out_ptr,
+                          1 if normalize else 0, stream))

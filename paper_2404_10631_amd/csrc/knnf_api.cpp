@@ -72,6 +72,9 @@ struct knnf_ctx {
     int next_slot = 0;
     unsigned long long* d_stats = nullptr;  // work counters while enabled
     bool stats_on = false;
+    // PC1 workspace: [per-block (min, max) pairs][npix doubles]
+    char* pc1_ws = nullptr;
+    size_t pc1_ws_bytes = 0;
 };
 
 namespace {
@@ -342,6 +345,10 @@ knnf_status knnf_destroy(knnf_ctx* ctx) {
         if (s.host) hipHostFree(s.host);
     }
     if (ctx->d_stats) hipFree(ctx->d_stats);
+    if (ctx->pc1_ws) {
+        hipDeviceSynchronize();
+        hipFree(ctx->pc1_ws);
+    }
     hipSetDevice(prev);
     delete ctx;
     return KNNF_OK;
@@ -405,6 +412,45 @@ knnf_status knnf_filter_batch(knnf_ctx* ctx, const knnf_frame* frames, int n,
         items[k].ntiles = knnf::tiles_of(f.H, f.W, p);
     }
     return knnf::launch_items(ctx, items.data(), n, p, stream);
+}
+
+knnf_status knnf_pc1(knnf_ctx* ctx, const float* cube, int64_t npix, int32_t bands,
+                     const double* mean, const double* vec, float* out, int32_t normalize,
+                     void* stream) {
+    if (npix < 1 || npix > KNNF_PC1_MAX_PIXELS)
+        return fail(KNNF_EINVAL, "knnf_pc1: npix %lld outside [1, 2^40]", (long long)npix);
+    if (bands < 1 || bands > KNNF_PC1_MAX_BANDS)
+        return fail(KNNF_EINVAL, "knnf_pc1: bands %d outside [1, %d]", bands, KNNF_PC1_MAX_BANDS);
+    if (!cube || !mean || !vec || !out) return fail(KNNF_EINVAL, "knnf_pc1: NULL pointer");
+    if (!ctx) return fail(KNNF_EINVAL, "knnf_pc1: NULL context");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    int prev = 0;
+    hipGetDevice(&prev);
+    if (prev != ctx->device) hipSetDevice(ctx->device);
+    struct Restore {
+        int prev, dev;
+        ~Restore() { if (prev != dev) hipSetDevice(prev); }
+    } restore{prev, ctx->device};
+    const size_t head = ((size_t)2 * knnf::pc1_max_blocks() * sizeof(double) + 255) & ~size_t(255);
+    const size_t need = head + (normalize ? (size_t)npix * sizeof(double) : 0);
+    if (ctx->pc1_ws_bytes < need) {
+        // grow: earlier launches may still use the old buffer
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "knnf_pc1: synchronize");
+        const size_t bytes = std::max(need, ctx->pc1_ws_bytes * 2);
+        if (ctx->pc1_ws) hipFree(ctx->pc1_ws);
+        ctx->pc1_ws = nullptr;
+        ctx->pc1_ws_bytes = 0;
+        e = hipMalloc((void**)&ctx->pc1_ws, bytes);
+        if (e != hipSuccess) return fail(KNNF_ENOMEM, "knnf_pc1 workspace: %s", hipGetErrorString(e));
+        ctx->pc1_ws_bytes = bytes;
+    }
+    double* pairs = (double*)ctx->pc1_ws;
+    double* ws = normalize ? (double*)(ctx->pc1_ws + head) : nullptr;
+    const int rc = knnf::launch_pc1(cube, npix, bands, mean, vec, out, ws, pairs, ctx->num_cu,
+                                    stream);
+    if (rc != 0) return hip_fail((hipError_t)rc, "knnf_pc1 launch");
+    return KNNF_OK;
 }
 
 knnf_status knnf_stats_enable(knnf_ctx* ctx, int on) {

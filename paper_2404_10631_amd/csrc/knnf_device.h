@@ -49,4 +49,11 @@ int launch_filter_items(const FrameDesc* d_frames, const uint32_t* d_task_start,
                         const uint32_t* d_tile_base, uint32_t nframes, uint32_t total_tasks,
                         const LaunchCfg& cfg, void* stream);
 
+// PC1 projection (defined in knnf_pc1.hip).  ws == nullptr: out = the centred
+// projection; otherwise ws (npix doubles) holds it, and out = its min-max
+// normalisation; pairs holds 2 * pc1_max_blocks() doubles (scratch).
+int pc1_max_blocks();
+int launch_pc1(const float* cube, int64_t npix, int bands, const double* mean, const double* vec,
+               float* out, double* ws, double* pairs, int num_cu, void* stream);
+
 }  // namespace knnf

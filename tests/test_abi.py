@@ -16,7 +16,7 @@ HEADER = os.path.join(ROOT, "include", "knnf.h")
 def _declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(knnf_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(knnf_[a-z0-9_]+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")
@@ -86,3 +86,17 @@ def test_null_context_is_einval(lib):
     assert lib.knnf_filter(None, ctypes.byref(f), None, None) == _lib.KNNF_EINVAL
     assert lib.knnf_filter_batch(None, ctypes.byref(f), 1, None, None) == _lib.KNNF_EINVAL
     assert lib.knnf_destroy(None) == _lib.KNNF_OK
+
+
+@pytest.mark.parametrize("kw,word", [
+    (dict(npix=0), "npix"), (dict(npix=(1 << 40) + 1), "npix"),
+    (dict(bands=0), "bands"), (dict(bands=4097), "bands"),
+    (dict(cube=None), "NULL"), (dict(mean=None), "NULL"), (dict(vec=None), "NULL"),
+    (dict(out=None), "NULL"), (dict(), "context"),
+])
+def test_pc1_validation(lib, kw, word):
+    a = dict(cube=0x1000, npix=100, bands=128, mean=0x2000, vec=0x3000, out=0x4000)
+    a.update(kw)
+    st = lib.knnf_pc1(None, a["cube"], a["npix"], a["bands"], a["mean"], a["vec"], a["out"], 1, None)
+    assert st == _lib.KNNF_EINVAL
+    assert word in _lib.last_error()
