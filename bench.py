@@ -123,10 +123,12 @@ def pc1_leg(ctx, stream, reps=20):
     # read back for the normalisation, the binary32 band written
     nbytes = npix * B * 4 + npix * 8 * 2 + npix * 4 + B * 16
     gbs = nbytes / (ms * 1e-3) / 1e9
+    rec = profile_record("pc1_project_brain480x380x128.md", "knnf_pc1.hip")
     return {"workload": f"brain-like cube W{W}xH{H}, {B} bands, normalised", "ms": round(ms, 5),
             "pixels_per_s": round(npix / (ms * 1e-3), 1), "bytes": nbytes,
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
-                         "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4)}}
+                         "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                         "traffic": (rec or {}).get("traffic_bytes_per_call")}}
 
 
 def batch_leg(ctx, plan, stream, reps=3):
@@ -159,7 +161,8 @@ P99_TARGET_MS = 10.0   # pre-registered per-frame latency target of the served s
 
 
 def serve_leg(ctx, plan, n_frames, rate,
-              sweep=(1000.0, 2000.0, 4000.0, 6000.0, 8000.0, 10000.0, 12000.0, 16000.0),
+              sweep=(1000.0, 2000.0, 4000.0, 6000.0, 8000.0, 10000.0, 11000.0, 12000.0, 14000.0,
+                     16000.0),
               sweep_frames=800):
     """Poisson stream of mixed frame sizes: continuous-batching server vs plain
     one-frame-at-a-time launches, both fed by the same arrival schedules."""
@@ -341,20 +344,25 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def measured_traffic(plan):
-    """HBM bytes per launch of the timed kernel from the committed counter
-    summary (FETCH_SIZE + WRITE_SIZE scaled by a plain copy), or None when the
-    kernel source or the plan changed since the counters were taken."""
+def profile_record(profile, source):
+    """The JSON record of a committed counter summary under profiles/, or None
+    when the kernel source changed since the counters were taken."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "filter_frame_kernel_brain480x380_K40_traffic.txt")
-    src = os.path.join(ROOT, "paper_2404_10631_amd", "csrc", "knnf_kernels.hip")
     try:
-        rec = json.loads(open(path).read().split("JSON:", 1)[1])
+        rec = json.loads(open(os.path.join(ROOT, "profiles", profile)).read().split("JSON:", 1)[1])
+        src = os.path.join(ROOT, "paper_2404_10631_amd", "csrc", source)
         digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except (OSError, IndexError, ValueError):
         return None
-    if rec.get("kernel_source_sha256") != digest or rec.get("plan") != plan:
+    return rec if rec.get("kernel_source_sha256") == digest else None
+
+
+def measured_traffic(plan):
+    """HBM bytes per launch of the timed filter kernel (FETCH_SIZE + WRITE_SIZE
+    scaled by a plain copy), or None when the kernel or the plan changed."""
+    rec = profile_record("filter_frame_kernel_brain480x380_K40_traffic.txt", "knnf_kernels.hip")
+    if rec is None or rec.get("plan") != plan:
         return None
     return rec.get("traffic_bytes_per_launch")
 
