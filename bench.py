@@ -140,7 +140,10 @@ def batch_leg(ctx, plan, stream, reps=3):
     for wl in (inputs.config2(), inputs.config3()):
         frames = [DeviceFrame(*f.make(), f.K, f.R, f.lam, with_nbr=False) for f in wl.frames]
         cfs = [f.as_c() for f in frames]
-        t_batch = time_gpu(lambda: _lib.knnf_filter_batch(ctx, cfs, plan, stream), reps)
+        # the batched schedule (search, tile shape, waves, launch mode) is
+        # picked by the library's autotuner on these frames
+        tuned = _lib.knnf_tune(ctx, cfs, 2, stream).as_dict()
+        t_batch = time_gpu(lambda: _lib.knnf_filter_batch(ctx, cfs, tuned, stream), reps)
 
         def plain():
             for c in cfs:
@@ -152,7 +155,8 @@ def batch_leg(ctx, plan, stream, reps=3):
                         "batched_pixels_per_s": round(px / t_batch, 1),
                         "plain_pixels_per_s": round(px / t_plain, 1),
                         "batched_ms": round(t_batch * 1e3, 4), "plain_ms": round(t_plain * 1e3, 4),
-                        "speedup": round(t_plain / t_batch, 3)}
+                        "speedup": round(t_plain / t_batch, 3), "tuned_plan": tuned,
+                        "plain_plan": plan}
         del frames
     return out
 
@@ -326,6 +330,12 @@ def main():
                        "p99": round(float(np.percentile(lat_ms, 99)), 5)},
         "roofline": roofline,
         "exhaustive_search": exhaustive,
+        # the paper's own figures, for context only: whole pipeline (PCA + SVM
+        # + KNN + transfers) per image on its hardware, lambda = 1, a 14-row
+        # window (Table 3, desktop GPUs)
+        "context": {"paper_rtx2080_whole_pipeline_s": {"PB2C1 493x375": 1.13, "PD1C1 1000x1000": 2.49},
+                    "paper_rtx2080_whole_pipeline_pixels_per_s": {"PB2C1 493x375": 163606,
+                                                                  "PD1C1 1000x1000": 401606}},
     }
     legs = set(args.legs.split(","))
     if "batch" in legs:

@@ -1,0 +1,134 @@
+"""GPU parity at the benchmark's full sizes, in the launch configurations the
+benchmark times: the 64 uneven brain-like frames and the 1024 dermatology-like
+50 x 50 frames in one batched launch, and the mixed S/M/L serving stream
+through the batching server.  Pixels are checked against the oracle at
+sampled positions (the oracle computes them one by one), plus every pixel of
+64 whole small frames; neighbour indices, distances and classes bit-exact,
+probabilities within 1e-6.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_10631_amd import _lib, inputs
+from paper_2404_10631_amd.frames import DeviceFrame, current_stream
+from paper_2404_10631_amd.serve import HostFrame, Server, replay
+
+pytestmark = pytest.mark.gpu
+
+PROB_TOL = 1e-6
+DEFAULT = None  # the context's default plan (pruned 2x4, persistent batches)
+GRID = dict(search=1, tile_rows=2, tile_cols=4, waves=1, launch=2)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    assert torch.cuda.is_available()
+    c = _lib.knnf_create(0)
+    yield c
+    _lib.knnf_destroy(c)
+
+
+def sample_pixels(H, W, n, rng):
+    """Corners, edge midpoints and n random pixels (linear indices)."""
+    fixed = [(0, 0), (0, W - 1), (H - 1, 0), (H - 1, W - 1), (H // 2, 0), (H // 2, W - 1),
+             (0, W // 2), (H - 1, W // 2)]
+    r = rng.integers(0, H, n)
+    c = rng.integers(0, W, n)
+    pix = np.array([i * W + j for i, j in fixed] + list(r * W + c), np.int64)
+    return np.unique(pix)
+
+
+def check_sampled(label, spec, data, outs, pix):
+    go, gc, gn, gd = outs
+    pc1, prob = data
+    ro, rc, rn, rd = oracle.knn_pixels(pc1, prob, spec.K, spec.R, spec.lam, pix)
+    H, W = spec.H, spec.W
+    fo = go.reshape(H * W, -1)[pix]
+    fc = gc.reshape(-1)[pix]
+    if gn is not None:
+        assert np.array_equal(gn.reshape(H * W, -1)[pix], rn), f"{label}: neighbours differ"
+        assert np.array_equal(gd.reshape(H * W, -1)[pix].view(np.uint32), rd.view(np.uint32)), \
+            f"{label}: distances differ"
+    assert np.array_equal(fc, rc), f"{label}: class differs"
+    assert float(np.max(np.abs(fo.astype(np.float64) - ro))) <= PROB_TOL, f"{label}: prob differs"
+
+
+@pytest.mark.parametrize("plan", [DEFAULT, GRID], ids=["persistent", "grid"])
+def test_config2_uneven_batch_full_size(ctx, plan):
+    """64 brain-like frames, H and W uniform in [50, 1000], K = 40, +-14 rows,
+    one batched launch; 128 sampled pixels per frame against the oracle."""
+    import torch
+
+    wl = inputs.config2()
+    say(f"config2: generating {len(wl.frames)} frames, {wl.pixels} pixels")
+    data = [s.make() for s in wl.frames]
+    frames = [DeviceFrame(p, q, s.K, s.R, s.lam, with_nbr=True) for s, (p, q) in zip(wl.frames, data)]
+    say(f"config2: one batched launch, plan={plan}")
+    _lib.knnf_filter_batch(ctx, [f.as_c() for f in frames], plan, current_stream())
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(7)
+    for k, (s, d, f) in enumerate(zip(wl.frames, data, frames)):
+        check_sampled(f"config2 frame {k} ({s.H}x{s.W})", s, d, f.results(),
+                      sample_pixels(s.H, s.W, 120, rng))
+    say("config2: sampled pixels bit-exact")
+
+
+def test_config3_small_frame_batch_full_size(ctx):
+    """1024 derma-like 50 x 50 frames, K = 16, +-7 rows, one batched launch:
+    64 whole frames at every pixel, 32 sampled pixels of every other frame."""
+    import torch
+
+    wl = inputs.config3()
+    say(f"config3: generating {len(wl.frames)} frames")
+    data = [s.make() for s in wl.frames]
+    frames = [DeviceFrame(p, q, s.K, s.R, s.lam, with_nbr=True) for s, (p, q) in zip(wl.frames, data)]
+    say("config3: one batched launch")
+    _lib.knnf_filter_batch(ctx, [f.as_c() for f in frames], DEFAULT, current_stream())
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(8)
+    whole = set(range(0, 1024, 16))
+    for k, (s, d, f) in enumerate(zip(wl.frames, data, frames)):
+        go, gc, gn, gd = f.results()
+        if k in whole:
+            ro, rc, rn, rd = oracle.knn_filter(d[0], d[1], s.K, s.R, s.lam)
+            assert np.array_equal(gn, rn) and np.array_equal(gc, rc), f"config3 frame {k}"
+            assert np.array_equal(gd.view(np.uint32), rd.view(np.uint32)), f"config3 frame {k}"
+            assert float(np.max(np.abs(go.astype(np.float64) - ro))) <= PROB_TOL
+        else:
+            check_sampled(f"config3 frame {k}", s, d, (go, gc, gn, gd),
+                          sample_pixels(s.H, s.W, 24, rng))
+    say("config3: 64 whole frames and sampled pixels bit-exact")
+
+
+def test_config4_served_mix_full_size(ctx):
+    """The serving stream's S/M/L classes at full size (50x50 K=16 +-7,
+    W480xH380 K=40 +-14, 1000x1000 K=40 +-14), Poisson arrivals, through the
+    batching server; every frame checked at sampled pixels."""
+    stream = inputs.serve_stream(n=40, rate_hz=2000.0, seed=11)
+    specs = [s for _, _, s in stream]
+    arrivals = [t for t, _, _ in stream]
+    say(f"config4: generating {len(specs)} frames "
+        f"({sum(1 for _, c, _ in stream if c == 'L')} of 1000x1000)")
+    data = [s.make() for s in specs]
+    hosts = [HostFrame(p, q, s.K, s.R, s.lam) for s, (p, q) in zip(specs, data)]
+    pool = 2 << 30
+    results = {}
+    say("config4: replaying through the server")
+    with Server(ctx, pool) as srv:
+        replay(srv, hosts, arrivals, keep=lambda k, v: results.__setitem__(k, srv.view_arrays(v)))
+    rng = np.random.default_rng(9)
+    for k, (s, d) in enumerate(zip(specs, data)):
+        go, gc, _, _ = results[k]
+        check_sampled(f"config4 frame {k} ({s.H}x{s.W})", s, d, (go, gc, None, None),
+                      sample_pixels(s.H, s.W, 64, rng))
+    say("config4: sampled pixels bit-exact")
