@@ -46,10 +46,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
-    ap.add_argument("--legs", default="plain,batch,serve,pc1",
+    ap.add_argument("--legs", default="plain,batch,serve,pc1,variants",
                     help="comma list of: plain (headline), batch (uneven / small-frame "
                          "batches), serve (Poisson mixed stream), pc1 (the projection "
-                         "step that produces the band)")
+                         "step that produces the band), variants (whole-frame window, "
+                         "lambda = 0)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (to scale HBM counters)")
     ap.add_argument("--serve-frames", type=int, default=2000)
@@ -88,6 +89,40 @@ def time_gpu(fn, reps):
         fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / reps
+
+
+def variants_leg(ctx, plan, stream):
+    """The filter's other work shapes on the brain-like W480 x H380 frame
+    (K = 40): the whole frame as the window (the paper's base definition), and
+    lambda = 0 (spectral distance only), with both searches; ms per frame."""
+    import torch
+
+    from paper_2404_10631_amd import _lib, inputs
+    from paper_2404_10631_amd.frames import DeviceFrame
+
+    spec = inputs.config1().frames[0]
+    pc1, prob = spec.make()
+    out = {}
+    for label, R, lam in (("window_pm14_lambda0.01", 14, 0.01),
+                          ("whole_frame_window_lambda0.01", spec.H - 1, 0.01),
+                          ("window_pm14_lambda0", 14, 0.0)):
+        df = DeviceFrame(pc1, prob, 40, R, lam, with_nbr=False)
+        c = df.as_c()
+        for sname, search in (("pruned", 1), ("exhaustive", 0)):
+            p = dict(plan, search=search)
+            reps = 3 if (search == 0 and R > 14) else 10
+            _lib.knnf_filter(ctx, c, p, stream)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                _lib.knnf_filter(ctx, c, p, stream)
+            e1.record()
+            torch.cuda.synchronize()
+            out[f"{label}_{sname}_ms"] = round(e0.elapsed_time(e1) / reps, 4)
+        del df
+    return out
 
 
 def pc1_leg(ctx, stream, reps=20):
@@ -344,6 +379,9 @@ def main():
     if "serve" in legs:
         print("bench: serve leg", file=sys.stderr, flush=True)
         out["serving"] = serve_leg(ctx, plan, args.serve_frames, args.serve_rate)
+    if "variants" in legs:
+        print("bench: variants leg", file=sys.stderr, flush=True)
+        out["variants"] = variants_leg(ctx, plan, stream)
     if "pc1" in legs:
         print("bench: pc1 leg", file=sys.stderr, flush=True)
         out["pc1_projection"] = pc1_leg(ctx, stream)

@@ -267,3 +267,39 @@ def test_work_counters(ctx):
     tiles = ((spec.H + 1) // 2) * ((spec.W + 7) // 8)
     assert te == tp == tiles
     assert pp < pe
+
+
+def test_lambda_zero_spectral_only(ctx):
+    """lambda = 0: the K nearest PC1 values in the window (a realistic band,
+    so distances tie only by value), both searches, every pixel."""
+    pc1, prob = inputs.g_brain(60, 90, 12)
+    ref = oracle.knn_filter(pc1, prob, 16, 7, 0.0)
+    for plan in (PRU24, EXH8):
+        say(f"lambda 0 realistic band plan={plan}")
+        assert_parity(run_gpu(ctx, pc1, prob, 16, 7, 0.0, plan), ref, "lambda0")
+
+
+def test_unwindowed_whole_frame(ctx):
+    """R beyond the frame: every pixel of the frame is a candidate (the
+    paper's base definition without a window), every pixel compared."""
+    pc1, prob = inputs.g_brain(96, 128, 13)
+    ref = oracle.knn_filter(pc1, prob, 40, 500, 0.01)
+    for plan in (PRU24, EXH8):
+        say(f"unwindowed 96x128 plan={plan}")
+        assert_parity(run_gpu(ctx, pc1, prob, 40, 500, 0.01, plan), ref, "unwindowed")
+
+
+def test_unwindowed_full_size_sampled(ctx):
+    """W 480 x H 380, K = 40, whole-frame window, pruned search: 300 sampled
+    pixels against the oracle (182,400 candidates each)."""
+    spec = inputs.config1().frames[0]
+    pc1, prob = spec.make()
+    H, W, K, R = spec.H, spec.W, 40, spec.H - 1
+    say("unwindowed full size")
+    go, gc, gn, gd = run_gpu(ctx, pc1, prob, K, R, spec.lam, PRU24)
+    pix = np.random.default_rng(31).choice(H * W, 300, replace=False)
+    ro, rc, rn, rd = oracle.knn_pixels(pc1, prob, K, R, spec.lam, pix)
+    assert np.array_equal(gn.reshape(H * W, K)[pix], rn)
+    assert np.array_equal(gc.reshape(-1)[pix], rc)
+    assert np.array_equal(gd.reshape(H * W, K)[pix].view(np.uint32), rd.view(np.uint32))
+    assert float(np.max(np.abs(go.reshape(H * W, -1)[pix].astype(np.float64) - ro))) <= PROB_TOL
