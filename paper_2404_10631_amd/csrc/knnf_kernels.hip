@@ -18,26 +18,25 @@
 // binary32 operation and fmaf is the only fused operation.
 //
 // Work decomposition (not the paper's; designed for 64-wide wavefronts):
-//   * One wavefront task = a vertical strip of Q query pixels at one column c,
-//     rows r0 .. r0+Q-1.  Sharing the column makes b depend on the candidate
-//     column only, so it is computed once per 64-column chunk.
-//   * Lanes sweep candidates: at each step lane L holds candidate column
-//     j = j0 + L of one window row; the row's I values are one coalesced
-//     256-byte load shared by all Q queries of the strip.
-//   * Selection per query is cooperative across the wavefront:
-//       pass A: the 64 candidates of a compact block around q (8 rows x 8
-//       columns where the window allows) are sorted with a 64-lane bitonic
-//       network; the K-th key is an upper bound tau on the final K-th key.
-//       pass B: every window candidate is tested against tau (one compare per
-//       pair); the rare survivors are appended to a per-query LDS buffer with
-//       ballot + mbcnt.  A full buffer is sorted and merged into the query's
-//       sorted top-K list, which tightens tau.
+//   * One wavefront task = a tile of QR x QC query pixels (default 2 x 4).
+//     Per-query state lives in VGPRs and a small per-wavefront LDS block.
+//   * pass A (bound): the 64 candidates of a compact block around each query
+//     (8 rows x 8 columns where the window allows) are evaluated and sorted
+//     for all Q queries at once by a segmented bitonic network; the K-th
+//     distance d_K bounds the query's final K-th key from above.
+//   * pass B (collect): candidates with d <= d_K are appended to a per-query
+//     LDS buffer with ballot + mbcnt; a full buffer is merged into a sorted
+//     per-query list, which tightens the bound.  Two scans:
+//       - pruned (default): 16-row x 4-column patches swept outward from the
+//         tile over the rows and column steps whose spatial lower bound is
+//         within some query's bound (bit-identical: every term of Eq. 1 is
+//         >= 0 and rounding is monotone);
+//       - exhaustive: every window row in 64-column chunks, four rows per
+//         group, one coalesced 256-byte load per row shared by all queries.
+//   * Final selection: one segmented sort of 32-bit packed keys (distance
+//     bits | buffer slot) with exact (d, idx) repair of equal distance parts.
 //   * The tail is fused: gather the K neighbours' probabilities (L2-resident),
 //     sum in key order, divide, argmax, and write the outputs.
-//   * Pruned search (optional, bit-identical): candidate rows and column chunks
-//     whose spatial part of Eq. 1 already exceeds tau are skipped; all terms of
-//     Eq. 1 are non-negative and rounding is monotone, so a skipped candidate
-//     always has d > tau.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -64,9 +63,6 @@ __device__ __forceinline__ uint32_t uniu(uint32_t v) {
 __device__ __forceinline__ uint64_t uni64(uint64_t v) {
     return ((uint64_t)uniu((uint32_t)(v >> 32)) << 32) | (uint64_t)uniu((uint32_t)v);
 }
-__device__ __forceinline__ float unif(float v) {
-    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
-}
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 __device__ __forceinline__ int mbcnt(uint64_t m) {
     return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
@@ -83,9 +79,6 @@ __device__ __forceinline__ uint32_t shfl(uint32_t v, int src) {
 }
 __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
     return ((uint64_t)shfl((uint32_t)(v >> 32), src) << 32) | (uint64_t)shfl((uint32_t)v, src);
-}
-__device__ __forceinline__ uint32_t xlane_read(uint32_t v, int lane) {
-    return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
 }
 __device__ __forceinline__ uint64_t make_key(float d, int idx) {
     return ((uint64_t)__float_as_uint(d) << 32) | (uint64_t)(uint32_t)idx;
@@ -155,31 +148,6 @@ __device__ __forceinline__ uint64_t merge64(uint64_t a, uint64_t b) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Compare-exchange of 32-bit values (min/max) for the pass-A bound.
-template <int S, int J>
-__device__ __forceinline__ void cx_u32(uint32_t& v) {
-    const int L = lane_id();
-    const uint32_t p = xlane<J>(v);
-    const bool keep_min = ((L & J) != 0) == (S < WAVE && (L & S) != 0);
-    v = keep_min ? min(v, p) : max(v, p);
-}
-
-template <int S, int J>
-__device__ __forceinline__ void stage_u32(uint32_t& v) {
-    cx_u32<S, J>(v);
-    if constexpr (J > 1) stage_u32<S, J / 2>(v);
-}
-
-__device__ __forceinline__ uint32_t sort64_u32(uint32_t v) {
-    stage_u32<2, 1>(v);
-    stage_u32<4, 2>(v);
-    stage_u32<8, 4>(v);
-    stage_u32<16, 8>(v);
-    stage_u32<32, 16>(v);
-    stage_u32<64, 32>(v);
-    return v;
-}
-
 // ---- segmented sorts: the Q queries of a tile sorted together.  Segment q
 // (64 elements) lives in lanes q*P .. q*P+P-1, P = 64 / E; lane L holds
 // elements e = (L % P) * E + r in x[r], r < E.
@@ -209,10 +177,6 @@ __device__ __forceinline__ uint32_t lanex(uint32_t v) {
         static_assert(X == 4 || X == 8 || X == 16 || X == 32, "unsupported lane permutation");
         return xlane<X>(v);
     }
-}
-template <int X>
-__device__ __forceinline__ uint64_t lanex64(uint64_t v) {
-    return ((uint64_t)lanex<X>((uint32_t)(v >> 32)) << 32) | (uint64_t)lanex<X>((uint32_t)v);
 }
 
 // The u32 network sorts bit patterns of non-negative binary32 values (pass-A
@@ -284,74 +248,6 @@ __device__ __forceinline__ void seg_sort_u32(uint32_t (&x)[E], int lp) {
     seg_stage_u32<E, 2>(x, lp);
 }
 
-// The same network over 64-bit keys (distance bits << 32 | index).
-template <int E, int KS>
-__device__ __forceinline__ void seg_mirror_key(uint64_t (&x)[E], int lp) {
-    if constexpr (KS <= E) {
-#pragma unroll
-        for (int r = 0; r < E; ++r) {
-            if (r & (KS / 2)) continue;
-            constexpr int M = KS - 1;
-            const uint64_t a = x[r], b = x[r ^ M];
-            const bool sw = b < a;
-            x[r] = sw ? b : a;
-            x[r ^ M] = sw ? a : b;
-        }
-    } else {
-        const bool upper = (lp & (KS / (2 * E))) != 0;
-        uint64_t p[E];
-#pragma unroll
-        for (int r = 0; r < E; ++r) p[r] = lanex64<KS / E - 1>(x[E - 1 - r]);
-#pragma unroll
-        for (int r = 0; r < E; ++r) {
-            const bool take = (p[r] < x[r]) != upper;
-            x[r] = take ? p[r] : x[r];
-        }
-    }
-}
-
-template <int E, int D>
-__device__ __forceinline__ void seg_half_key(uint64_t (&x)[E], int lp) {
-    if constexpr (D < E) {
-#pragma unroll
-        for (int r = 0; r < E; ++r) {
-            if (r & D) continue;
-            const uint64_t a = x[r], b = x[r | D];
-            const bool sw = b < a;
-            x[r] = sw ? b : a;
-            x[r | D] = sw ? a : b;
-        }
-    } else {
-        const bool upper = (lp & (D / E)) != 0;
-#pragma unroll
-        for (int r = 0; r < E; ++r) {
-            const uint64_t p = lanex64<D / E>(x[r]);
-            const bool take = (p < x[r]) != upper;
-            x[r] = take ? p : x[r];
-        }
-    }
-}
-
-template <int E, int KS, int D>
-__device__ __forceinline__ void seg_halves_key(uint64_t (&x)[E], int lp) {
-    if constexpr (D >= 1) {
-        seg_half_key<E, D>(x, lp);
-        seg_halves_key<E, KS, D / 2>(x, lp);
-    }
-}
-
-template <int E, int KS>
-__device__ __forceinline__ void seg_stage_key(uint64_t (&x)[E], int lp) {
-    seg_mirror_key<E, KS>(x, lp);
-    seg_halves_key<E, KS, KS / 4>(x, lp);
-    if constexpr (KS < WAVE) seg_stage_key<E, KS * 2>(x, lp);
-}
-
-template <int E>
-__device__ __forceinline__ void seg_sort_key(uint64_t (&x)[E], int lp) {
-    seg_stage_key<E, 2>(x, lp);
-}
-
 // Per-wavefront LDS state of one tile of QR x QC query pixels.
 template <int QR, int QC>
 struct alignas(16) TileState {
@@ -368,11 +264,10 @@ struct alignas(16) TileState {
     int cnt[Q];               // pending entries (mirror of the scan's registers)
 };
 
-// The exhaustive scan also keeps the full bound key (index included after a
-// merge) and a table of row terms; the pruned scan needs neither.
+// The exhaustive scan also keeps a table of row terms; the pruned scan
+// computes them per lane.
 template <int QR, int QC, bool PRUNE>
 struct alignas(16) TileLds : TileState<QR, QC> {
-    uint64_t tau[QR * QC];          // current bound on the K-th key of each query
     float a2t[A2ROWS + A2PAD][QR];  // fl32(a*a) for a block of window rows (+inf: inactive)
 };
 template <int QR, int QC>
@@ -625,23 +520,6 @@ __device__ __forceinline__ void scan_pruned(TileState<QR, QC>& S, const FrameDes
     }
 }
 
-// Pass A: lane L's candidate in a compact block of query (r, c)'s window: 8 x 8
-// pixels where the window allows (fewer rows, more columns near short
-// windows); returns false for lanes past the frame's right edge.
-__device__ __forceinline__ bool block_cand(const FrameDesc& f, int r, int c, int L, int& i, int& j) {
-    const int i0 = max(0, r - f.R), i1 = min(f.H - 1, r + f.R);
-    const int nr = i1 - i0 + 1;
-    const int lbr = nr >= 8 ? 3 : (nr >= 4 ? 2 : (nr >= 2 ? 1 : 0));
-    const int br = 1 << lbr;
-    const int lbc = 6 - lbr;
-    const int bc = 1 << lbc;
-    const int rb = min(max(r - br / 2, i0), i1 - br + 1);
-    const int cb = max(0, min(c - bc / 2, f.W - bc));
-    i = rb + (L >> lbc);
-    j = cb + (L & (bc - 1));
-    return j < f.W;
-}
-
 // Process one tile: query pixels (r0 + qr, c0 + qc), qr < QR, qc < QC.
 template <int QR, int QC, bool PRUNE>
 __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const FrameDesc& f, int r0,
@@ -736,7 +614,6 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
         if (L < Q) {
             const bool ok = (L / QC) < nqr && (L % QC) < nqc;
             const uint32_t dk = S.list[L][K - 1];
-            if constexpr (!PRUNE) S.tau[L] = ok ? (((uint64_t)dk << 32) | 0xffffffffull) : 0ull;
             S.tauhi[L] = ok ? dk : 0u;
         }
         wave_sync();
@@ -769,7 +646,6 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
         const int nch = (W + WAVE - 1) / WAVE;
         const int cc = (c0 + (nqc - 1) / 2) / WAVE;
         int tab_base = -1;       // first row of the a2 table contents
-        uint32_t exact = 0;      // queries whose bound carries a real index (after a merge)
 
         for (int t = 0; t < 2 * nch; ++t) {
             const int m = (t & 1) ? cc + (t + 1) / 2 : cc - t / 2;
@@ -777,6 +653,7 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
             const int J = m * WAVE;
             const int j = J + L;
             const bool valid = j < W;
+            const uint64_t vm = ballot(valid);
             const int jl = valid ? j : W - 1;
             // lanes past the right edge get b = +inf, so every distance there is
             // +inf (never below a finite bound; the append step checks `valid`)
@@ -834,7 +711,7 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
                             if (qr < nqr && z >= a) pairs += (unsigned long long)(z - a + 1) * nqc * nvl;
                         }
                     }
-                    uint32_t ovf = 0;  // queries whose pending buffer could not take a row
+                    uint32_t ovf = 0;  // queries whose buffer cannot take this group's survivors
     #pragma unroll
                     for (int q = 0; q < Q; ++q) {
                         const int qr = q / QC, qc = q % QC;
@@ -848,79 +725,69 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
                         const uint32_t mn = min(min(__float_as_uint(d[0]), __float_as_uint(d[1])),
                                                 min(__float_as_uint(d[2]), __float_as_uint(d[3])));
                         if (ballot(mn <= th[q])) {
-                            // rare: some candidate of the group may belong to the
-                            // query.  Until the query's first merge its bound is
-                            // (d_K, max index), so key <= tau is d <= d_K; the
-                            // whole group is appended if it fits, otherwise (or
-                            // with an exact bound) the group goes to the merge path.
+                            // rare: some candidate of the group is within the
+                            // bound; append the group's survivors if they fit
                             const int r = r0 + qr;
-                            bool ok[4];
+                            bool rok[4];  // group rows inside the query row's window
                             uint64_t mu[4];
-                            int ntot = 0;
+                            int n = 0;
     #pragma unroll
                             for (int u = 0; u < 4; ++u) {
                                 const int i = i0 + u;
-                                const bool rowok = i <= hi && i >= r - R && i <= r + R;
-                                ok[u] = valid && rowok && __float_as_uint(d[u]) <= th[q];
-                                mu[u] = ballot(ok[u]);
-                                ntot += __builtin_popcountll(mu[u]);
+                                rok[u] = i <= hi && i >= r - R && i <= r + R;
+                                mu[u] = rok[u] ? ballot(__float_as_uint(d[u]) <= th[q]) & vm : 0ull;
+                                n += __builtin_popcountll(mu[u]);
                             }
-                            if (((exact >> q) & 1u) || cnt[q] + ntot > WAVE) {
-                                ovf |= 1u << q;
-                            } else {
+                            if (cnt[q] + n <= WAVE) {
     #pragma unroll
                                 for (int u = 0; u < 4; ++u) {
-                                    if (ok[u])
+                                    if (valid && rok[u] && __float_as_uint(d[u]) <= th[q])
                                         S.pend[q][cnt[q] + mbcnt(mu[u])] = make_key(d[u], (i0 + u) * W + j);
                                     cnt[q] += __builtin_popcountll(mu[u]);
                                 }
+                            } else {
+                                ovf |= 1u << q;
                             }
                         }
                     }
                     if (ovf) {
-                        // rare: merge full buffers and append the group exactly
+                        // rare: merge full buffers into the sorted lists (which
+                        // tightens the bounds), appending the group row by row
     #pragma unroll
                         for (int q = 0; q < Q; ++q)
                             if (L == 0) S.cnt[q] = cnt[q];
                         wave_sync();
-                        exact |= ovf;
                         while (ovf) {
                             const int q = __builtin_ctz(ovf);
                             ovf &= ovf - 1;
                             const int qr = q / QC, qc = q % QC;
                             const int r = r0 + qr;
                             int cq = uni(S.cnt[q]);
-                            uint64_t tq = uni64(S.tau[q]);
+                            uint32_t thq = uniu(S.tauhi[q]);
                             const float bq = valid ? feat(lam, c0 + qc) - feat(lam, j) : pinf;
                             const float iqq = S.iq[q];
-    #pragma unroll
                             for (int u = 0; u < 4; ++u) {
                                 const int i = i0 + u;
-                                if (i > hi || i < r - R || i > r + R) continue;
+                                if (qr >= nqr || i > hi || i < r - R || i > r + R) continue;
                                 const float a2q = S.a2t[g + u][qr];
                                 const float e = iqq - ip[u];
                                 const float du = fmaf(e, e, fmaf(bq, bq, a2q));
-                                const int idx = i * W + j;
-                                bool ok = valid && make_key(du, idx) <= tq;
-                                uint64_t msk = ballot(ok);
+                                uint64_t msk = ballot(__float_as_uint(du) <= thq) & vm;
                                 if (!msk) continue;
-                                int n = __builtin_popcountll(msk);
-                                if (cq + n > WAVE) {
-                                    const uint64_t nb2 = flush_query(S, f, r0, c0, q, cq, false);
+                                if (cq + __builtin_popcountll(msk) > WAVE) {
+                                    const uint64_t kth = flush_query(S, f, r0, c0, q, cq, false);
                                     cq = 0;
-                                    tq = nb2 < tq ? nb2 : tq;
-                                    ok = valid && make_key(du, idx) <= tq;
-                                    msk = ballot(ok);
-                                    n = __builtin_popcountll(msk);
+                                    if (kth != KEY_INF) thq = min(thq, (uint32_t)(kth >> 32));
+                                    msk = ballot(__float_as_uint(du) <= thq) & vm;
                                 }
-                                if (ok) S.pend[q][cq + mbcnt(msk)] = make_key(du, idx);
-                                cq += n;
+                                if (valid && __float_as_uint(du) <= thq)
+                                    S.pend[q][cq + mbcnt(msk)] = make_key(du, i * W + j);
+                                cq += __builtin_popcountll(msk);
                             }
                             wave_sync();
                             if (L == 0) {
                                 S.cnt[q] = cq;
-                                S.tau[q] = tq;
-                                S.tauhi[q] = (uint32_t)(tq >> 32);
+                                S.tauhi[q] = thq;
                             }
                             wave_sync();
                         }
