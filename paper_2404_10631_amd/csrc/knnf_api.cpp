@@ -60,6 +60,32 @@ size_t off_counter(size_t cap) { return off_tile_base(cap) + round256(cap * size
 size_t slot_bytes(size_t cap) { return off_counter(cap) + 256; }
 
 constexpr int kSlots = 4;
+// Work items every slot holds from context creation on, so that batched
+// launches of up to this many items (the serving steps) never allocate.
+constexpr size_t kSlotItems = 64;
+
+// Give a slot room for at least n work items.  The slot must be idle (its
+// last launch finished).  Allocating synchronises the device, so it is done
+// up front for kSlotItems and only grows for larger batches.
+hipError_t grow_slot(BatchSlot& s, size_t n) {
+    if (s.cap >= n) return hipSuccess;
+    size_t cap = std::max<size_t>(kSlotItems, s.cap);
+    while (cap < n) cap *= 2;
+    if (s.dev) hipFree(s.dev);
+    if (s.host) hipHostFree(s.host);
+    s.dev = s.host = nullptr;
+    s.cap = 0;
+    hipError_t e = hipMalloc(&s.dev, slot_bytes(cap));
+    if (e != hipSuccess) return e;
+    e = hipHostMalloc(&s.host, slot_bytes(cap), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        hipFree(s.dev);
+        s.dev = nullptr;
+        return e;
+    }
+    s.cap = cap;
+    return hipSuccess;
+}
 
 }  // namespace
 
@@ -218,23 +244,8 @@ knnf_status launch_items(knnf_ctx* ctx, const WorkItem* items, int n, const knnf
         if (e != hipSuccess) return hip_fail(e, "batch slot wait");
         s.recorded = false;
     }
-    if (s.cap < (size_t)n) {
-        size_t cap = std::max<size_t>(64, s.cap);
-        while (cap < (size_t)n) cap *= 2;
-        if (s.dev) hipFree(s.dev);
-        if (s.host) hipHostFree(s.host);
-        s.dev = s.host = nullptr;
-        s.cap = 0;
-        e = hipMalloc(&s.dev, slot_bytes(cap));
-        if (e != hipSuccess) return fail(KNNF_ENOMEM, "batch table: %s", hipGetErrorString(e));
-        e = hipHostMalloc(&s.host, slot_bytes(cap), hipHostMallocDefault);
-        if (e != hipSuccess) {
-            hipFree(s.dev);
-            s.dev = nullptr;
-            return fail(KNNF_ENOMEM, "batch staging: %s", hipGetErrorString(e));
-        }
-        s.cap = cap;
-    }
+    e = grow_slot(s, (size_t)n);
+    if (e != hipSuccess) return fail(KNNF_ENOMEM, "batch table: %s", hipGetErrorString(e));
     knnf::FrameDesc* hf = (knnf::FrameDesc*)s.host;
     uint32_t* hts = (uint32_t*)((char*)s.host + off_task_start(s.cap));
     uint32_t* htb = (uint32_t*)((char*)s.host + off_tile_base(s.cap));
@@ -320,10 +331,11 @@ knnf_status knnf_create(knnf_ctx** out, int device) {
         c->num_cu = prop.multiProcessorCount;
     for (auto& s : c->slots) {
         e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
+        if (e == hipSuccess) e = grow_slot(s, kSlotItems);
         if (e != hipSuccess) {
             hipSetDevice(prev);
             knnf_destroy(c);
-            return hip_fail(e, "hipEventCreate");
+            return hip_fail(e, "knnf_create: batch table slots");
         }
     }
     hipSetDevice(prev);
