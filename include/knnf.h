@@ -134,7 +134,8 @@ typedef struct {
  *                           consecutive tasks from a counter until none is left
  *   KNNF_LAUNCH_GRID        one wavefront per task; the hardware dispatcher
  *                           balances the load
- * 0 means the context's default (persistent).
+ * 0 means the context's default (grid: faster than persistent on uneven
+ * and small-frame batches on MI355X).
  */
 typedef enum { KNNF_LAUNCH_DEFAULT = 0, KNNF_LAUNCH_PERSISTENT = 1, KNNF_LAUNCH_GRID = 2 } knnf_launch;
 
@@ -162,9 +163,10 @@ knnf_status knnf_filter(knnf_ctx* ctx, const knnf_frame* frame,
                         const knnf_plan* plan, void* stream);
 
 /*
- * Filter n frames of possibly different sizes and parameters with one
- * persistent launch on `stream`: workgroups pull per-wavefront tasks from a
- * shared counter, largest frames first.  Every frame's outputs are bitwise
+ * Filter n frames of possibly different sizes and parameters with one launch
+ * on `stream` over a table of per-wavefront tile tasks, largest frames first
+ * (plan->launch: one wavefront per task, or a persistent grid whose
+ * wavefronts claim tasks from a shared counter).  Every frame's outputs are bitwise
  * equal to knnf_filter() of that frame alone.  The frame table is copied to
  * the context's device workspace with an asynchronous copy on `stream`; the
  * caller's array may be reused when the call returns.  Calls on one context
@@ -254,8 +256,11 @@ double knnf_server_clock(void);
 
 /*
  * Create a server on `ctx` that sub-allocates frames from the device buffer
- * `pool` (pool_bytes bytes, caller-owned, must outlive the server).  Starts
- * one scheduler thread.  opts may be NULL (batched mode, defaults).
+ * `pool` (pool_bytes >= 4096 bytes, 256-byte aligned as hipMalloc returns it,
+ * caller-owned, must outlive the server; its contents are overwritten).
+ * Starts one scheduler thread after one small warm-up operation on each of
+ * its streams.  opts may be NULL (batched mode, defaults).  KNNF_EINVAL for
+ * bad arguments, KNNF_EDEVICE if a stream cannot be set up.
  */
 knnf_status knnf_server_create(knnf_server** out, knnf_ctx* ctx, void* pool,
                                size_t pool_bytes, const knnf_server_opts* opts);

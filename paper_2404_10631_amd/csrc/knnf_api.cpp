@@ -111,7 +111,7 @@ knnf_plan default_plan() {
     p.tile_rows = 2;
     p.tile_cols = 4;
     p.waves = 1;
-    p.launch = KNNF_LAUNCH_PERSISTENT;
+    p.launch = KNNF_LAUNCH_GRID;
     return p;
 }
 

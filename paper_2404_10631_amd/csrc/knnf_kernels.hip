@@ -422,16 +422,14 @@ __device__ __forceinline__ void scan_pruned(TileState<QR, QC>& S, const FrameDes
                 const int st = n + L;
                 const int jc = side == 0 ? c0 + 4 * (ncen + st) : c0 - 4 * (st + 1);
                 const int jn = side == 0 ? jc : jc + 3;  // the step's column nearest the tile
-                bool live = false;
-                if (side == 0 ? jc < W : jn >= 0) {
-                    const float fj = feat(lam, jn);
+                const float fj = feat(lam, jn);
+                uint64_t m = 0;
 #pragma unroll
-                    for (int q = 0; q < Q; ++q) {
-                        const float b = feat(lam, c0 + q % QC) - fj;
-                        live |= __float_as_uint(fmaf(b, b, a2n[q / QC])) <= th[q];
-                    }
+                for (int q = 0; q < Q; ++q) {
+                    const float b = feat(lam, c0 + q % QC) - fj;
+                    m |= ballot(__float_as_uint(fmaf(b, b, a2n[q / QC])) <= th[q]);
                 }
-                const uint64_t m = ballot(live);
+                m &= ballot(side == 0 ? jc < W : jn >= 0);
                 const int k = (~m) ? (int)__builtin_ctzll(~m) : WAVE;
                 n += k;
                 if (k < WAVE) break;
@@ -520,6 +518,26 @@ __device__ __forceinline__ void scan_pruned(TileState<QR, QC>& S, const FrameDes
     }
 }
 
+// s + v[0] + v[1] + ... + v[N-1], left to right, where v[u] is the float at
+// pb + lst[u] * rowb: all N gathers are issued before the first add.  lst is
+// 16-byte aligned and N a multiple of 4.
+template <int N>
+__device__ __forceinline__ float gather_add(float s, const char* __restrict__ pb,
+                                            const uint32_t* lst, uint32_t rowb) {
+    float v[N];
+#pragma unroll
+    for (int u = 0; u < N; u += 4) {
+        const uint4 id = *(const uint4*)(lst + u);
+        v[u + 0] = *(const float*)(pb + (uint64_t)id.x * rowb);
+        v[u + 1] = *(const float*)(pb + (uint64_t)id.y * rowb);
+        v[u + 2] = *(const float*)(pb + (uint64_t)id.z * rowb);
+        v[u + 3] = *(const float*)(pb + (uint64_t)id.w * rowb);
+    }
+#pragma unroll
+    for (int u = 0; u < N; ++u) s = s + v[u];
+    return s;
+}
+
 // Process one tile: query pixels (r0 + qr, c0 + qc), qr < QR, qc < QC.
 template <int QR, int QC, bool PRUNE>
 __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const FrameDesc& f, int r0,
@@ -556,55 +574,31 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
         // I of the segment's query pixel (NaN for pixels off the frame)
         const float iqs = sok ? pc1[(uint32_t)r * (uint32_t)W + (uint32_t)c] : qnan;
         const float frq = feat(lam, r), fcq = feat(lam, c);
-        // every lane loads (columns past the edge clamped: rows rb .. rb+br-1
-        // are inside the frame even for queries off its bottom edge), so all
-        // E loads are in flight together
+        // Element e = u * P + lp of the block is row rb + (e >> lbc), column
+        // cb + (e & (bc - 1)): the P lanes of a segment read P consecutive
+        // columns of one row per load, so a load touches few cache lines.
+        // Every lane loads (columns past the right edge clamped and given
+        // +inf; rows rb .. rb+br-1 are inside the frame even for queries off
+        // its bottom edge), so all E loads are in flight together.
         uint32_t x[E];
-        if constexpr (E <= 8) {
-            // blocks are at least 8 columns wide, so a lane's E elements lie
-            // in one row, at consecutive columns
-            const int e0 = lp * E;
-            const int ib = rb + (e0 >> lbc);
-            const int jb = cb + (e0 & (bc - 1));
-            const float* __restrict__ rowp = pc1 + (size_t)(uint32_t)ib * (uint32_t)W;
-            float pv[E];
-            if (W >= WAVE) {
+        float pv[E];
 #pragma unroll
-                for (int u = 0; u < E; ++u) pv[u] = rowp[jb + u];
-            } else {
+        for (int u = 0; u < E; ++u) {
+            const int e = u * P + lp;
+            const int i = rb + (e >> lbc);
+            const int j = min(cb + (e & (bc - 1)), W - 1);
+            pv[u] = pc1[(uint32_t)i * (uint32_t)W + (uint32_t)j];
+        }
 #pragma unroll
-                for (int u = 0; u < E; ++u) pv[u] = rowp[min(jb + u, W - 1)];
-            }
-            const float a = frq - feat(lam, ib);
-            const float a2 = a * a;
-#pragma unroll
-            for (int u = 0; u < E; ++u) {
-                const int j = jb + u;
-                const float b = fcq - feat(lam, j);
-                const float ee = iqs - pv[u];
-                const uint32_t d = __float_as_uint(fmaf(ee, ee, fmaf(b, b, a2)));
-                x[u] = (sok && j < W) ? d : 0x7f800000u;  // +inf: no candidate
-            }
-        } else {
-            float pv[E];
-#pragma unroll
-            for (int u = 0; u < E; ++u) {
-                const int e = lp * E + u;
-                const int i = rb + (e >> lbc);
-                const int j = min(cb + (e & (bc - 1)), W - 1);
-                pv[u] = pc1[(uint32_t)i * (uint32_t)W + (uint32_t)j];
-            }
-#pragma unroll
-            for (int u = 0; u < E; ++u) {
-                const int e = lp * E + u;
-                const int i = rb + (e >> lbc);
-                const int j = cb + (e & (bc - 1));
-                const float a = frq - feat(lam, i);
-                const float b = fcq - feat(lam, j);
-                const float ee = iqs - pv[u];
-                const uint32_t d = __float_as_uint(fmaf(ee, ee, fmaf(b, b, a * a)));
-                x[u] = (sok && j < W) ? d : 0x7f800000u;  // +inf: no candidate
-            }
+        for (int u = 0; u < E; ++u) {
+            const int e = u * P + lp;
+            const int i = rb + (e >> lbc);
+            const int j = cb + (e & (bc - 1));
+            const float a = frq - feat(lam, i);
+            const float b = fcq - feat(lam, j);
+            const float ee = iqs - pv[u];
+            const uint32_t d = __float_as_uint(fmaf(ee, ee, fmaf(b, b, a * a)));
+            x[u] = (sok && j < W) ? d : 0x7f800000u;  // +inf: no candidate
         }
         if (lp == 0) S.iq[sq] = iqs;
         seg_sort_u32<E>(x, lp);
@@ -899,31 +893,9 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
         const uint32_t* lst = S.list[q];
         float s = 0.0f;
         int k = 0;
-        for (; k + 16 <= K; k += 16) {
-            float v[16];
-#pragma unroll
-            for (int u = 0; u < 16; u += 4) {
-                const uint4 id = *(const uint4*)(lst + k + u);
-                v[u + 0] = *(const float*)(pb + (uint64_t)id.x * rowb);
-                v[u + 1] = *(const float*)(pb + (uint64_t)id.y * rowb);
-                v[u + 2] = *(const float*)(pb + (uint64_t)id.z * rowb);
-                v[u + 3] = *(const float*)(pb + (uint64_t)id.w * rowb);
-            }
-#pragma unroll
-            for (int u = 0; u < 16; ++u) s = s + v[u];
-        }
+        for (; k + 16 <= K; k += 16) s = gather_add<16>(s, pb, lst + k, rowb);
         if (k + 8 <= K) {
-            float v[8];
-#pragma unroll
-            for (int u = 0; u < 8; u += 4) {
-                const uint4 id = *(const uint4*)(lst + k + u);
-                v[u + 0] = *(const float*)(pb + (uint64_t)id.x * rowb);
-                v[u + 1] = *(const float*)(pb + (uint64_t)id.y * rowb);
-                v[u + 2] = *(const float*)(pb + (uint64_t)id.z * rowb);
-                v[u + 3] = *(const float*)(pb + (uint64_t)id.w * rowb);
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) s = s + v[u];
+            s = gather_add<8>(s, pb, lst + k, rowb);
             k += 8;
         }
         for (; k < K; ++k) s = s + *(const float*)(pb + (uint64_t)lst[k] * rowb);
@@ -966,13 +938,14 @@ __global__ void __launch_bounds__(WPB * WAVE) filter_frame_kernel(FrameDesc f) {
     __shared__ TileLds<QR, QC, PRUNE> lds[WPB];
     const int w = uni((int)(threadIdx.x >> 6));
     const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    const int ntc = (f.W + QC - 1) / QC;
-    const long long ntiles = (long long)((f.H + QR - 1) / QR) * ntc;
-    const long long s = (long long)b * WPB + w;
+    // tiles <= H * W < 2^31 (checked on the host): 32-bit index arithmetic
+    const uint32_t ntc = (uint32_t)((f.W + QC - 1) / QC);
+    const uint32_t ntiles = (uint32_t)((f.H + QR - 1) / QR) * ntc;
+    const uint32_t s = (uint32_t)b * WPB + (uint32_t)w;
     if (s >= ntiles) return;
-    const int band = (int)(s / ntc);
-    const int tc = (int)(s - (long long)band * ntc);
-    process_tile<QR, QC, PRUNE>(lds[w], f, band * QR, tc * QC);
+    const uint32_t band = s / ntc;
+    const uint32_t tc = s - band * ntc;
+    process_tile<QR, QC, PRUNE>(lds[w], f, (int)band * QR, (int)tc * QC);
 }
 
 // Persistent batched kernel: each wavefront claims tile tasks from one global
@@ -981,9 +954,12 @@ __global__ void __launch_bounds__(WPB * WAVE) filter_frame_kernel(FrameDesc f) {
 // task_start[k] .. task_start[k+1]-1.  Claims go out in task order, so the
 // whole device sweeps neighbouring tiles (which share window rows) at the same
 // time.  Every wavefront leaves the loop after one failed claim, so the grid
-// always drains.
+// always drains.  The claim loop's state would otherwise push the 8-query
+// tiles past 80 VGPRs (4 wavefronts per SIMD instead of the 6 of the other
+// launches); the hint trades that for a few dwords of scratch per tile.
 template <int QR, int QC, int WPB, bool PRUNE>
 __global__ void __launch_bounds__(WPB * WAVE)
+__attribute__((amdgpu_waves_per_eu(QR * QC == 8 ? 6 : 1)))
 filter_batch_kernel(const FrameDesc* __restrict__ frames, const uint32_t* __restrict__ task_start,
                     const uint32_t* __restrict__ tile_base, uint32_t nframes, uint32_t total_tasks,
                     uint32_t claim, uint32_t* counter) {

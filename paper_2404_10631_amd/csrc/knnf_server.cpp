@@ -302,6 +302,8 @@ knnf_status knnf_server_create(knnf_server** out, knnf_ctx* ctx, void* pool, siz
                                const knnf_server_opts* opts) {
     if (!out || !ctx || !pool || pool_bytes < 4096)
         return knnf::set_error(KNNF_EINVAL, "knnf_server_create: bad arguments");
+    if ((uintptr_t)pool & 255)
+        return knnf::set_error(KNNF_EINVAL, "knnf_server_create: pool not 256-byte aligned");
     *out = nullptr;
     knnf_server_opts o{};
     if (opts) o = *opts;
@@ -334,10 +336,30 @@ knnf_status knnf_server_create(knnf_server** out, knnf_ctx* ctx, void* pool, siz
         ok = ok && hipStreamCreateWithFlags(&st.stream, hipStreamNonBlocking) == hipSuccess;
         ok = ok && hipEventCreateWithFlags(&st.done, hipEventDisableTiming) == hipSuccess;
     }
+    // Warm every stream: HIP sets up a stream's hardware queue and its copy
+    // path from pinned host memory on first use, which took about 6 ms each
+    // and delayed the first frames a new server admitted.  The warm-up copies
+    // one zero word from a pinned buffer to the start of the pool (which
+    // holds no frame yet) and launches one tiny kernel per compute stream.
+    if (ok) {
+        uint32_t* zero = nullptr;
+        ok = hipHostMalloc((void**)&zero, 256, hipHostMallocDefault) == hipSuccess;
+        if (ok) {
+            *zero = 0;
+            ok = hipMemcpyAsync(s->pool, zero, sizeof *zero, hipMemcpyHostToDevice,
+                                s->copy_stream) == hipSuccess &&
+                 hipStreamSynchronize(s->copy_stream) == hipSuccess;
+            hipHostFree(zero);
+        }
+        for (Step& st : s->steps) {
+            ok = ok && knnf::launch_zero_counter((uint32_t*)s->pool, st.stream) == 0 &&
+                 hipStreamSynchronize(st.stream) == hipSuccess;
+        }
+    }
     hipSetDevice(prev);
     if (!ok) {
         knnf_server_destroy(s);
-        return knnf::set_error(KNNF_EDEVICE, "knnf_server_create: stream or event creation failed");
+        return knnf::set_error(KNNF_EDEVICE, "knnf_server_create: stream setup failed");
     }
     s->thread = std::thread(scheduler, s);
     *out = s;

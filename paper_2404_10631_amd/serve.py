@@ -95,7 +95,8 @@ def replay(server: Server, frames, arrivals, warmup: int = 0, keep=None, timeout
     """Submit frames[k] at server-clock time t0 + arrivals[k]; release each frame
     as soon as it is done (after `keep(k, view)` if given).
 
-    Returns a dict with per-frame latencies (seconds) and the makespan.
+    Returns a dict with per-frame latencies (seconds), the server's per-frame
+    timestamps (arrival, admission, first launch, completion) and the makespan.
     """
     h = server.handle
     n = len(frames)
@@ -137,7 +138,8 @@ def replay(server: Server, frames, arrivals, warmup: int = 0, keep=None, timeout
     t = np.array([info[i] for i in range(n)])
     lat = t[:, 3] - t[:, 0]
     sel = np.arange(n) >= warmup
-    return {"latency_s": lat, "measured": sel, "t_arrival": t[:, 0], "t_done": t[:, 3],
+    return {"latency_s": lat, "measured": sel, "t_arrival": t[:, 0], "t_admit": t[:, 1],
+            "t_launch": t[:, 2], "t_done": t[:, 3],
             "makespan_s": float(t[sel, 3].max() - t[sel, 0].min())}
 
 

@@ -19,8 +19,8 @@ from paper_2404_10631_amd.serve import HostFrame, Server, replay
 pytestmark = pytest.mark.gpu
 
 PROB_TOL = 1e-6
-DEFAULT = None  # the context's default plan (pruned 2x4, persistent batches)
-GRID = dict(search=1, tile_rows=2, tile_cols=4, waves=1, launch=2)
+PERSISTENT = dict(search=1, tile_rows=2, tile_cols=4, waves=1, launch=1)
+GRID = dict(search=1, tile_rows=2, tile_cols=4, waves=1, launch=2)  # the context's default
 
 
 def say(msg):
@@ -63,7 +63,7 @@ def check_sampled(label, spec, data, outs, pix):
     assert float(np.max(np.abs(fo.astype(np.float64) - ro))) <= PROB_TOL, f"{label}: prob differs"
 
 
-@pytest.mark.parametrize("plan", [DEFAULT, GRID], ids=["persistent", "grid"])
+@pytest.mark.parametrize("plan", [PERSISTENT, GRID], ids=["persistent", "grid"])
 def test_config2_uneven_batch_full_size(ctx, plan):
     """64 brain-like frames, H and W uniform in [50, 1000], K = 40, +-14 rows,
     one batched launch; 128 sampled pixels per frame against the oracle."""
@@ -84,21 +84,30 @@ def test_config2_uneven_batch_full_size(ctx, plan):
 
 
 def test_config3_small_frame_batch_full_size(ctx):
-    """1024 derma-like 50 x 50 frames, K = 16, +-7 rows, one batched launch:
-    64 whole frames at every pixel, 32 sampled pixels of every other frame."""
+    """1024 derma-like 50 x 50 frames, K = 16, +-7 rows, one batched launch
+    (the default grid launch; the persistent launch must give the same bits):
+    64 whole frames at every pixel, 24 sampled pixels of every other frame."""
     import torch
 
     wl = inputs.config3()
     say(f"config3: generating {len(wl.frames)} frames")
     data = [s.make() for s in wl.frames]
     frames = [DeviceFrame(p, q, s.K, s.R, s.lam, with_nbr=True) for s, (p, q) in zip(wl.frames, data)]
-    say("config3: one batched launch")
-    _lib.knnf_filter_batch(ctx, [f.as_c() for f in frames], DEFAULT, current_stream())
+    say("config3: one batched launch, persistent")
+    _lib.knnf_filter_batch(ctx, [f.as_c() for f in frames], PERSISTENT, current_stream())
+    torch.cuda.synchronize()
+    persistent = [f.results() for f in frames]
+    for f in frames:
+        f.clear_outputs()
+    say("config3: one batched launch, default plan")
+    _lib.knnf_filter_batch(ctx, [f.as_c() for f in frames], None, current_stream())
     torch.cuda.synchronize()
     rng = np.random.default_rng(8)
     whole = set(range(0, 1024, 16))
     for k, (s, d, f) in enumerate(zip(wl.frames, data, frames)):
         go, gc, gn, gd = f.results()
+        for x, y in zip((go, gc, gn, gd), persistent[k]):
+            assert np.array_equal(x, y), f"config3 frame {k}: launch modes differ"
         if k in whole:
             ro, rc, rn, rd = oracle.knn_filter(d[0], d[1], s.K, s.R, s.lam)
             assert np.array_equal(gn, rn) and np.array_equal(gc, rc), f"config3 frame {k}"

@@ -211,7 +211,8 @@ def test_batch_matches_single_frames_and_oracle(ctx):
              inputs.FrameSpec("brain", 130, 61, 5, K=40, R=14),
              inputs.FrameSpec("unif", 1, 1, 6, K=1, R=0),
              inputs.FrameSpec("brain", 64, 64, 7, K=24, R=3, lam=0.05)]
-    for plan in (EXH8, PRU8, dict(search=1, tile_rows=1, tile_cols=16, waves=1)):
+    shapes = (EXH8, PRU8, dict(search=1, tile_rows=1, tile_cols=16, waves=1))
+    for plan in [dict(p, launch=launch) for p in shapes for launch in (1, 2)]:
         say(f"batch of {len(specs)} plan={plan}")
         data = [s.make() for s in specs]
         batch = [DeviceFrame(p, q, s.K, s.R, s.lam) for s, (p, q) in zip(specs, data)]
