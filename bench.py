@@ -59,24 +59,51 @@ def parse():
 
 
 def cpu_baseline(spec, pc1, prob, target_s):
-    """Oracle throughput on a bounded random sample of the frame's pixels."""
+    """Oracle throughput on a bounded random sample of the frame's pixels, on
+    all host threads (the reported value) and on one thread (a smaller
+    sample); pixels/s and window pairs/s."""
     import oracle
 
     nt = oracle.max_threads()
     H, W = spec.H, spec.W
     rng = np.random.default_rng(77)
+
+    def pairs_of(pix):
+        r = np.asarray(pix) // W
+        rows = np.minimum(H - 1, r + spec.R) - np.maximum(0, r - spec.R) + 1
+        return int(np.sum(rows)) * W
+
+    def timed(pix, threads):
+        t0 = time.perf_counter()
+        oracle.knn_pixels(pc1, prob, spec.K, spec.R, spec.lam, pix, with_nbr=False,
+                          nthreads=threads)
+        return max(time.perf_counter() - t0, 1e-6)
+
     probe = rng.integers(0, H * W, 512)
-    t0 = time.perf_counter()
-    oracle.knn_pixels(pc1, prob, spec.K, spec.R, spec.lam, probe, with_nbr=False, nthreads=nt)
-    dt = max(time.perf_counter() - t0, 1e-3)
+    dt = max(timed(probe, nt), 1e-3)
     n = int(min(H * W, max(2048, 512 * target_s / dt)))
     pix = rng.integers(0, H * W, n)
-    t0 = time.perf_counter()
-    oracle.knn_pixels(pc1, prob, spec.K, spec.R, spec.lam, pix, with_nbr=False, nthreads=nt)
-    dt = time.perf_counter() - t0
+    dt = timed(pix, nt)
+    # one thread: about a quarter of the multi-threaded time budget
+    n1 = int(max(256, min(n, 0.25 * target_s * n / dt / max(nt, 1))))
+    pix1 = rng.integers(0, H * W, n1)
+    dt1 = timed(pix1, 1)
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": n / dt, "unit": "pixels/s", "cores": nt, "kind": "oracle",
             "sample": f"{n} random pixels of the W480xH380 brain-like frame (K=40, +-14 rows), "
-                      f"{dt:.1f} s on {nt} threads"}
+                      f"{dt:.1f} s on {nt} threads",
+            "pairs_per_s": pairs_of(pix) / dt, "cpu_model": model,
+            "single_thread": {"value": n1 / dt1, "unit": "pixels/s",
+                              "pairs_per_s": pairs_of(pix1) / dt1,
+                              "sample": f"{n1} random pixels, {dt1:.1f} s on 1 thread"}}
 
 
 def time_gpu(fn, reps):
@@ -200,8 +227,8 @@ P99_TARGET_MS = 10.0   # pre-registered per-frame latency target of the served s
 
 
 def serve_leg(ctx, plan, n_frames, rate,
-              sweep=(1000.0, 2000.0, 4000.0, 6000.0, 8000.0, 10000.0, 11000.0, 12000.0, 14000.0,
-                     16000.0),
+              sweep=(400.0, 800.0, 1000.0, 1600.0, 2000.0, 3200.0, 4000.0, 6000.0, 8000.0,
+                     10000.0, 11000.0, 12000.0, 14000.0, 16000.0),
               sweep_frames=800):
     """Poisson stream of mixed frame sizes: continuous-batching server vs plain
     one-frame-at-a-time launches, both fed by the same arrival schedules."""

@@ -134,3 +134,17 @@ def test_server_errors(ctx):
         _lib.knnf_server_release(srv.handle, tk)
         with pytest.raises(_lib.KnnfError):
             _lib.knnf_server_release(srv.handle, tk)
+
+
+def test_server_pool_must_be_aligned(ctx):
+    """The pool is sub-allocated at 256-byte offsets and the server's stream
+    warm-up writes its first word: a misaligned or tiny pool is rejected."""
+    import torch
+
+    pool = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    for ptr, size in ((pool.data_ptr() + 16, (1 << 20) - 16), (pool.data_ptr(), 1024)):
+        with pytest.raises(_lib.KnnfError) as ei:
+            _lib.knnf_server_create(ctx, ptr, size)
+        assert ei.value.status == _lib.KNNF_EINVAL
+    h = _lib.knnf_server_create(ctx, pool.data_ptr(), 1 << 20)
+    _lib.knnf_server_destroy(h)
