@@ -40,8 +40,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--plan", default="pruned", choices=["exhaustive", "pruned"])
-    ap.add_argument("--tile-rows", type=int, default=2)
-    ap.add_argument("--tile-cols", type=int, default=4)
+    ap.add_argument("--tile-rows", type=int, default=1)
+    ap.add_argument("--tile-cols", type=int, default=8)
     ap.add_argument("--waves", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample")

@@ -117,8 +117,8 @@ typedef enum { KNNF_SEARCH_EXHAUSTIVE = 0, KNNF_SEARCH_PRUNED = 1 } knnf_search;
  *   waves         wavefronts per workgroup; 1, 2 or 4
  *   launch        knnf_launch (batched launches only)
  * A zero tile, wave or launch field means "the context's default" (initially a pruned
- * search with 2 x 4 tiles and one wavefront per workgroup); search is always
- * taken from the plan (0 = exhaustive).
+ * search with 1 x 8 tiles, one wavefront per workgroup and grid launches);
+ * search is always taken from the plan (0 = exhaustive).
  */
 typedef struct {
     int32_t search;

@@ -108,8 +108,8 @@ namespace {
 knnf_plan default_plan() {
     knnf_plan p{};
     p.search = KNNF_SEARCH_PRUNED;
-    p.tile_rows = 2;
-    p.tile_cols = 4;
+    p.tile_rows = 1;
+    p.tile_cols = 8;
     p.waves = 1;
     p.launch = KNNF_LAUNCH_GRID;
     return p;

@@ -933,8 +933,14 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     return (b & 7) * per + (b >> 3);
 }
 
+// 8-query tiles are held to 80 VGPRs (six wavefronts per SIMD, the LDS
+// limit too): without the hint some instantiations took 81-90 registers and
+// ran at five, which cost the batched 1x8 launch 11 %.
+#define KNNF_WAVES_PER_EU(QR, QC) __attribute__((amdgpu_waves_per_eu((QR) * (QC) == 8 ? 6 : 1)))
+
 template <int QR, int QC, int WPB, bool PRUNE>
-__global__ void __launch_bounds__(WPB * WAVE) filter_frame_kernel(FrameDesc f) {
+__global__ void __launch_bounds__(WPB * WAVE) KNNF_WAVES_PER_EU(QR, QC)
+filter_frame_kernel(FrameDesc f) {
     __shared__ TileLds<QR, QC, PRUNE> lds[WPB];
     const int w = uni((int)(threadIdx.x >> 6));
     const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
@@ -955,11 +961,10 @@ __global__ void __launch_bounds__(WPB * WAVE) filter_frame_kernel(FrameDesc f) {
 // whole device sweeps neighbouring tiles (which share window rows) at the same
 // time.  Every wavefront leaves the loop after one failed claim, so the grid
 // always drains.  The claim loop's state would otherwise push the 8-query
-// tiles past 80 VGPRs (4 wavefronts per SIMD instead of the 6 of the other
-// launches); the hint trades that for a few dwords of scratch per tile.
+// tiles to 110 VGPRs (four wavefronts per SIMD); held at 80 they spill a few
+// dwords to scratch, reloaded once per tile.
 template <int QR, int QC, int WPB, bool PRUNE>
-__global__ void __launch_bounds__(WPB * WAVE)
-__attribute__((amdgpu_waves_per_eu(QR * QC == 8 ? 6 : 1)))
+__global__ void __launch_bounds__(WPB * WAVE) KNNF_WAVES_PER_EU(QR, QC)
 filter_batch_kernel(const FrameDesc* __restrict__ frames, const uint32_t* __restrict__ task_start,
                     const uint32_t* __restrict__ tile_base, uint32_t nframes, uint32_t total_tasks,
                     uint32_t claim, uint32_t* counter) {
@@ -998,7 +1003,7 @@ filter_batch_kernel(const FrameDesc* __restrict__ frames, const uint32_t* __rest
 // Non-persistent batched kernel over the same work table: one wavefront per
 // task, the hardware dispatcher balances the load, XCD-aware block order.
 template <int QR, int QC, int WPB, bool PRUNE>
-__global__ void __launch_bounds__(WPB * WAVE)
+__global__ void __launch_bounds__(WPB * WAVE) KNNF_WAVES_PER_EU(QR, QC)
 filter_items_kernel(const FrameDesc* __restrict__ frames, const uint32_t* __restrict__ task_start,
                     const uint32_t* __restrict__ tile_base, uint32_t nframes,
                     uint32_t total_tasks) {

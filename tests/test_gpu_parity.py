@@ -22,7 +22,7 @@ PROB_TOL = 1e-6
 SHAPES = [(1, 8), (1, 16), (2, 4), (2, 8), (4, 4)]
 EXH8 = dict(search=0, tile_rows=2, tile_cols=8, waves=2)
 PRU8 = dict(search=1, tile_rows=2, tile_cols=8, waves=2)
-# the default plan and the other 8-query shape
+# the two 8-query shapes (1 x 8 is the context's default)
 PRU24 = dict(search=1, tile_rows=2, tile_cols=4, waves=1)
 PRU18 = dict(search=1, tile_rows=1, tile_cols=8, waves=1)
 TIE_PLANS = (EXH8, PRU8, PRU24, PRU18)
