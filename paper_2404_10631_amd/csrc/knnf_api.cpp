@@ -246,22 +246,53 @@ knnf_status launch_items(knnf_ctx* ctx, const WorkItem* items, int n, const knnf
     }
     e = grow_slot(s, (size_t)n);
     if (e != hipSuccess) return fail(KNNF_ENOMEM, "batch table: %s", hipGetErrorString(e));
-    knnf::FrameDesc* hf = (knnf::FrameDesc*)s.host;
-    uint32_t* hts = (uint32_t*)((char*)s.host + off_task_start(s.cap));
-    uint32_t* htb = (uint32_t*)((char*)s.host + off_tile_base(s.cap));
-    uint32_t acc = 0;
-    for (int k = 0; k < n; ++k) {
-        hf[k] = items[k].f;
-        hf[k].stats = ctx->stats_on ? ctx->d_stats : nullptr;
-        hts[k] = acc;
-        htb[k] = items[k].tile0;
-        acc += items[k].ntiles;
-    }
-    hts[n] = acc;
     hipStream_t hs = (hipStream_t)stream;
-    // one copy of the whole table prefix: descriptors, prefix, first tiles
-    e = hipMemcpyAsync(s.dev, s.host, off_counter(s.cap), hipMemcpyHostToDevice, hs);
-    if (e != hipSuccess) return hip_fail(e, "batch table copy");
+    constexpr size_t kDescWords = sizeof(knnf::FrameDesc) / 4;
+    static_assert(sizeof(knnf::FrameDesc) % 4 == 0, "descriptor size");
+    if ((size_t)n * (kDescWords + 2) + 1 <= (size_t)knnf::kTableWords) {
+        // small table (a serving step): written by a kernel that receives it
+        // as its argument, so this thread never waits on a copy
+        knnf::TableWords t;
+        uint32_t* tw = t.w;
+        const size_t nd = (size_t)n * kDescWords;
+        uint32_t acc = 0;
+        for (int k = 0; k < n; ++k) {
+            knnf::FrameDesc d = items[k].f;
+            d.stats = ctx->stats_on ? ctx->d_stats : nullptr;
+            std::memcpy(tw + (size_t)k * kDescWords, &d, sizeof d);
+            tw[nd + k] = acc;                // task prefix
+            tw[nd + n + 1 + k] = items[k].tile0;  // first tiles
+            acc += items[k].ntiles;
+        }
+        tw[nd + n] = acc;
+        t.src[0] = 0;
+        t.dst[0] = 0;
+        t.len[0] = (uint32_t)nd;
+        t.src[1] = (uint32_t)nd;
+        t.dst[1] = (uint32_t)(off_task_start(s.cap) / 4);
+        t.len[1] = (uint32_t)n + 1;
+        t.src[2] = (uint32_t)(nd + n + 1);
+        t.dst[2] = (uint32_t)(off_tile_base(s.cap) / 4);
+        t.len[2] = (uint32_t)n;
+        const int rc = knnf::launch_put_table(t, (uint32_t*)s.dev, stream);
+        if (rc != 0) return hip_fail((hipError_t)rc, "batch table write");
+    } else {
+        knnf::FrameDesc* hf = (knnf::FrameDesc*)s.host;
+        uint32_t* hts = (uint32_t*)((char*)s.host + off_task_start(s.cap));
+        uint32_t* htb = (uint32_t*)((char*)s.host + off_tile_base(s.cap));
+        uint32_t acc = 0;
+        for (int k = 0; k < n; ++k) {
+            hf[k] = items[k].f;
+            hf[k].stats = ctx->stats_on ? ctx->d_stats : nullptr;
+            hts[k] = acc;
+            htb[k] = items[k].tile0;
+            acc += items[k].ntiles;
+        }
+        hts[n] = acc;
+        // one copy of the whole table prefix: descriptors, prefix, first tiles
+        e = hipMemcpyAsync(s.dev, s.host, off_counter(s.cap), hipMemcpyHostToDevice, hs);
+        if (e != hipSuccess) return hip_fail(e, "batch table copy");
+    }
     uint32_t* d_ctr = (uint32_t*)((char*)s.dev + off_counter(s.cap));
     const knnf::LaunchCfg cfg = to_cfg(p);
     int rc;

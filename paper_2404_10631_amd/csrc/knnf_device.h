@@ -37,6 +37,17 @@ int launch_filter_batch(const FrameDesc* d_frames, const uint32_t* d_task_start,
 // Zero the batched kernel's claim counter.
 int launch_zero_counter(uint32_t* d_counter, void* stream);
 
+// A batch table small enough to travel as a kernel argument: run k copies
+// len[k] words from w[src[k]] to d_base[dst[k]].  Writing a small table this
+// way needs no host-to-device copy, which could hold up the launching thread
+// for milliseconds.
+constexpr int kTableWords = 880;
+struct TableWords {
+    uint32_t w[kTableWords];
+    uint32_t src[3], dst[3], len[3];
+};
+int launch_put_table(const TableWords& t, uint32_t* d_base, void* stream);
+
 // A range of tiles of one frame, the unit of a batched launch.
 struct WorkItem {
     FrameDesc f;

@@ -1118,4 +1118,14 @@ int launch_zero_counter(uint32_t* d_counter, void* stream) {
     return (int)hipGetLastError();
 }
 
+__global__ void __launch_bounds__(256) put_table_kernel(TableWords t, uint32_t* __restrict__ base) {
+    for (int r = 0; r < 3; ++r)
+        for (uint32_t k = threadIdx.x; k < t.len[r]; k += blockDim.x) base[t.dst[r] + k] = t.w[t.src[r] + k];
+}
+
+int launch_put_table(const TableWords& t, uint32_t* d_base, void* stream) {
+    hipLaunchKernelGGL(put_table_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, t, d_base);
+    return (int)hipGetLastError();
+}
+
 }  // namespace knnf
