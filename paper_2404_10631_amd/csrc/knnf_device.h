@@ -48,6 +48,11 @@ struct TableWords {
 };
 int launch_put_table(const TableWords& t, uint32_t* d_base, void* stream);
 
+// Copy na words a -> da and nb words b -> db with one small kernel (the
+// sources may be device-mapped pinned host memory).
+int launch_copy_pair(const uint32_t* a, uint32_t* da, uint32_t na, const uint32_t* b,
+                     uint32_t* db, uint32_t nb, void* stream);
+
 // A range of tiles of one frame, the unit of a batched launch.
 struct WorkItem {
     FrameDesc f;

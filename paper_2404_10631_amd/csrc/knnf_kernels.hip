@@ -1128,4 +1128,43 @@ int launch_put_table(const TableWords& t, uint32_t* d_base, void* stream) {
     return (int)hipGetLastError();
 }
 
+// Four independent loads in flight per thread: reads of mapped host memory
+// have long latency.
+__device__ __forceinline__ uint32_t pair_word(const uint32_t* __restrict__ a, uint32_t na,
+                                              const uint32_t* __restrict__ b, uint32_t k) {
+    return k < na ? a[k] : b[k - na];
+}
+__device__ __forceinline__ void pair_put(uint32_t* __restrict__ da, uint32_t na,
+                                         uint32_t* __restrict__ db, uint32_t k, uint32_t v) {
+    if (k < na)
+        da[k] = v;
+    else
+        db[k - na] = v;
+}
+
+__global__ void __launch_bounds__(256)
+copy_pair_kernel(const uint32_t* __restrict__ a, uint32_t* __restrict__ da, uint32_t na,
+                 const uint32_t* __restrict__ b, uint32_t* __restrict__ db, uint32_t nb) {
+    const uint32_t n = na + nb;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    for (; k + 3 * stride < n; k += 4 * stride) {
+        uint32_t v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = pair_word(a, na, b, k + u * stride);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pair_put(da, na, db, k + u * stride, v[u]);
+    }
+    for (; k < n; k += stride) pair_put(da, na, db, k, pair_word(a, na, b, k));
+}
+
+int launch_copy_pair(const uint32_t* a, uint32_t* da, uint32_t na, const uint32_t* b,
+                     uint32_t* db, uint32_t nb, void* stream) {
+    const uint32_t n = na + nb;
+    const uint32_t blocks = std::max<uint32_t>(1, std::min<uint32_t>(128, (n + 1023) / 1024));
+    hipLaunchKernelGGL(copy_pair_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, a, da,
+                       na, b, db, nb);
+    return (int)hipGetLastError();
+}
+
 }  // namespace knnf

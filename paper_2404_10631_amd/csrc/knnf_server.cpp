@@ -3,8 +3,10 @@
 // Frames arrive from the host at any time.  A scheduler thread
 //   1. admits queued frames in arrival order while the caller's device pool
 //      has room (first-fit sub-allocation; the head of the queue is never
-//      overtaken, so no frame starves) and copies their inputs to the pool on
-//      a copy stream;
+//      overtaken, so no frame starves) and hands them to a copier thread,
+//      which enqueues the copies of their inputs on a copy stream (a copy
+//      call can hold its thread for milliseconds when the copy stream is
+//      backed up; the scheduler keeps launching and reaping meanwhile);
 //   2. builds GPU steps: one batched launch over tile ranges of all admitted
 //      frames in arrival order, up to a tile budget, so a large frame is
 //      processed in slices and later arrivals join the next step (a lone
@@ -79,7 +81,7 @@ class PoolAllocator {
     std::map<size_t, size_t> free_;
 };
 
-enum JobState { QUEUED, ADMITTED, DONE, RELEASED };
+enum JobState { QUEUED, COPYING, ADMITTED, DONE, RELEASED };
 
 struct Job {
     uint64_t ticket = 0;
@@ -91,6 +93,8 @@ struct Job {
     int outstanding = 0;          // launched steps holding tiles of this job
     uint32_t waited = 0;          // compute streams (bit per step slot) told to wait for its copy
     hipEvent_t copied = nullptr;  // inputs are in the pool
+    const void* map_pc1 = nullptr;   // device views of small pinned inputs (else null)
+    const void* map_prob = nullptr;
     double t_arrival = 0, t_admit = 0, t_launch = -1, t_done = 0;
 };
 
@@ -118,17 +122,40 @@ struct knnf_server {
     std::condition_variable cv;
     std::unordered_map<uint64_t, Job> jobs;
     std::deque<uint64_t> queue;   // submitted, not admitted
+    std::deque<uint64_t> copyq;   // granted pool memory, copies not yet enqueued
     std::deque<uint64_t> ready;   // admitted, tiles left to launch
+    std::condition_variable copy_cv;
+    bool copier_busy = false;     // the copier is enqueueing a frame's copies
     uint64_t next_ticket = 1;
     size_t unfinished = 0;
     std::atomic<bool> stop{false};
     std::thread thread;
+    std::thread copier;
     knnf_status sticky = KNNF_OK;
 
     explicit knnf_server(size_t pool_bytes) : alloc(pool_bytes) {}
 };
 
 namespace {
+
+// When the copy stream is backed up, inputs of at most this many bytes that
+// sit in pinned, device-mapped host memory are copied by a kernel on the copy
+// stream: a host-to-device copy call then sometimes held its thread for
+// 7-11 ms, and every frame queued behind it waited as long.  An idle copy
+// stream, and larger inputs, keep the copy engine, which is faster.
+constexpr size_t kKernelCopyMax = 4u << 20;
+
+// Device address of pinned host memory at p, or null if the runtime does not
+// report p as device-mapped host memory.
+const void* device_view(const void* p) {
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();  // not registered: leave no error behind
+        return nullptr;
+    }
+    if (a.type != hipMemoryTypeHost || !a.devicePointer || !a.hostPointer) return nullptr;
+    return (const char*)a.devicePointer + ((const char*)p - (const char*)a.hostPointer);
+}
 
 hipEvent_t take_event(knnf_server* s) {
     if (!s->event_pool.empty()) {
@@ -165,7 +192,25 @@ void place(Job& j, char* base) {
     d.out_dist = j.hf.with_nbr ? (float*)put(px * j.hf.K * 4) : nullptr;
 }
 
-// Admission: FIFO while the pool has room.  Called with the lock held.
+bool copy_stream_idle(knnf_server* s) {
+    const bool idle = hipStreamQuery(s->copy_stream) == hipSuccess;
+    (void)hipGetLastError();  // "not ready" is an answer, not an error
+    return idle;
+}
+
+// Enqueue a frame's input copies and the event marking their end.
+hipError_t enqueue_copies(knnf_server* s, void* d1, const void* h1, size_t n1, void* d2,
+                          const void* h2, size_t n2, hipEvent_t ev) {
+    hipError_t e = ev ? hipSuccess : hipErrorOutOfMemory;
+    if (e == hipSuccess) e = hipMemcpyAsync(d1, h1, n1, hipMemcpyHostToDevice, s->copy_stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d2, h2, n2, hipMemcpyHostToDevice, s->copy_stream);
+    if (e == hipSuccess) e = hipEventRecord(ev, s->copy_stream);
+    return e;
+}
+
+// Admission: FIFO while the pool has room.  With no copy pending anywhere the
+// scheduler enqueues the frame's copies itself (the lowest latency); otherwise
+// the frame goes to the copier thread.  Called with the lock held.
 void admit(knnf_server* s) {
     while (!s->queue.empty()) {
         Job& j = s->jobs[s->queue.front()];
@@ -173,23 +218,74 @@ void admit(knnf_server* s) {
         if (!s->alloc.alloc(j.bytes, &off)) return;
         j.off = off;
         place(j, s->pool);
-        const size_t px = (size_t)j.hf.H * (size_t)j.hf.W;
-        hipError_t e = hipMemcpyAsync((void*)j.dev.pc1, j.hf.pc1, px * 4, hipMemcpyHostToDevice,
-                                      s->copy_stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync((void*)j.dev.prob, j.hf.prob, px * j.hf.C * 4,
-                               hipMemcpyHostToDevice, s->copy_stream);
-        j.copied = take_event(s);
-        if (e == hipSuccess && j.copied) e = hipEventRecord(j.copied, s->copy_stream);
-        if (e != hipSuccess || !j.copied) {
-            s->sticky = KNNF_EDEVICE;
-            return;
-        }
-        j.state = ADMITTED;
-        j.t_admit = now_s();
         j.ntiles = knnf::tiles_of(j.hf.H, j.hf.W, s->plan);
         s->queue.pop_front();
-        s->ready.push_back(j.ticket);
+        if (s->copyq.empty() && !s->copier_busy && copy_stream_idle(s)) {
+            const size_t px = (size_t)j.hf.H * (size_t)j.hf.W;
+            j.copied = take_event(s);
+            const hipError_t e =
+                enqueue_copies(s, (void*)j.dev.pc1, j.hf.pc1, px * 4, (void*)j.dev.prob, j.hf.prob,
+                               px * (size_t)j.hf.C * 4, j.copied);
+            if (e != hipSuccess) {
+                s->sticky = KNNF_EDEVICE;
+                return;
+            }
+            j.state = ADMITTED;
+            j.t_admit = now_s();
+            s->ready.push_back(j.ticket);
+        } else {
+            j.state = COPYING;
+            s->copyq.push_back(j.ticket);
+            s->copy_cv.notify_one();
+        }
+    }
+}
+
+// Copier thread: enqueues each admitted frame's input copies and the event
+// marking their end, without the lock held, then makes the frame ready.
+void copier(knnf_server* s) {
+    hipSetDevice(s->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        s->copy_cv.wait(lk, [s] { return s->stop.load() || !s->copyq.empty(); });
+        if (s->stop.load()) return;
+        const uint64_t tk = s->copyq.front();
+        s->copyq.pop_front();
+        s->copier_busy = true;
+        hipEvent_t ev = take_event(s);
+        const Job& jc = s->jobs[tk];  // not erased before DONE
+        const size_t px = (size_t)jc.hf.H * (size_t)jc.hf.W;
+        void* d1 = (void*)jc.dev.pc1;
+        void* d2 = (void*)jc.dev.prob;
+        const void* h1 = jc.hf.pc1;
+        const void* h2 = jc.hf.prob;
+        const void* m1 = jc.map_pc1;
+        const void* m2 = jc.map_prob;
+        const size_t n1 = px * 4, n2 = px * (size_t)jc.hf.C * 4;
+        lk.unlock();
+        hipError_t e;
+        if (ev && m1 && m2 && !copy_stream_idle(s)) {
+            e = (hipError_t)knnf::launch_copy_pair((const uint32_t*)m1, (uint32_t*)d1,
+                                                   (uint32_t)(n1 / 4), (const uint32_t*)m2,
+                                                   (uint32_t*)d2, (uint32_t)(n2 / 4), s->copy_stream);
+            if (e == hipSuccess) e = hipEventRecord(ev, s->copy_stream);
+        } else {
+            e = enqueue_copies(s, d1, h1, n1, d2, h2, n2, ev);
+        }
+        lk.lock();
+        s->copier_busy = false;
+        if (e != hipSuccess) {
+            // the frame never becomes ready; polls and drain report the error
+            s->sticky = KNNF_EDEVICE;
+            if (ev) s->event_pool.push_back(ev);
+            continue;
+        }
+        Job& j = s->jobs[tk];
+        j.copied = ev;
+        j.state = ADMITTED;
+        j.t_admit = now_s();
+        s->ready.push_back(tk);
+        s->cv.notify_one();
     }
 }
 
@@ -288,6 +384,11 @@ void scheduler(knnf_server* s) {
             // Nothing completed or launched: wait briefly for a submission or
             // for GPU progress (completion is observed by polling events).
             s->cv.wait_for(lk, std::chrono::microseconds(20));
+        } else {
+            // let the copier and the caller's polls take the lock in between
+            lk.unlock();
+            std::this_thread::yield();
+            lk.lock();
         }
     }
 }
@@ -362,6 +463,7 @@ knnf_status knnf_server_create(knnf_server** out, knnf_ctx* ctx, void* pool, siz
         return knnf::set_error(KNNF_EDEVICE, "knnf_server_create: stream setup failed");
     }
     s->thread = std::thread(scheduler, s);
+    s->copier = std::thread(copier, s);
     *out = s;
     return KNNF_OK;
 }
@@ -382,6 +484,13 @@ knnf_status knnf_server_submit(knnf_server* s, const knnf_host_frame* f, uint64_
     knnf_status st = knnf::validate_frame(&v, 0);
     if (st != KNNF_OK) return st;
     const size_t bytes = knnf_frame_bytes(f->H, f->W, f->C, f->K, f->with_nbr ? 1 : 0);
+    const void* m1 = nullptr;
+    const void* m2 = nullptr;
+    if ((size_t)f->H * (size_t)f->W * (size_t)(f->C + 1) * 4 <= kKernelCopyMax) {
+        m1 = device_view(f->pc1);
+        m2 = device_view(f->prob);
+        if (!m1 || !m2) m1 = m2 = nullptr;
+    }
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->sticky != KNNF_OK) return knnf::set_error(s->sticky, "server failed earlier");
     if (bytes > s->alloc.size())
@@ -394,6 +503,8 @@ knnf_status knnf_server_submit(knnf_server* s, const knnf_host_frame* f, uint64_
     j.hf = *f;
     j.bytes = bytes;
     j.t_arrival = f->t_arrival >= 0 ? f->t_arrival : now_s();
+    j.map_pc1 = m1;
+    j.map_prob = m2;
     s->jobs[j.ticket] = j;
     s->queue.push_back(j.ticket);
     ++s->unfinished;
@@ -458,9 +569,16 @@ knnf_status knnf_server_drain(knnf_server* s, double timeout_s) {
 
 knnf_status knnf_server_destroy(knnf_server* s) {
     if (!s) return KNNF_OK;
-    s->stop.store(true);
+    {
+        // set under the lock, so a thread between its check and its wait
+        // cannot miss the notification
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop.store(true);
+    }
     s->cv.notify_all();
+    s->copy_cv.notify_all();
     if (s->thread.joinable()) s->thread.join();
+    if (s->copier.joinable()) s->copier.join();
     int prev = 0;
     hipGetDevice(&prev);
     hipSetDevice(s->device);

@@ -23,6 +23,10 @@ class HostFrame:
 
         self.pc1 = torch.from_numpy(np.ascontiguousarray(pc1, np.float32)).pin_memory()
         self.prob = torch.from_numpy(np.ascontiguousarray(prob, np.float32)).pin_memory()
+        # The first device copy from a pinned buffer costs milliseconds in the
+        # HIP runtime; pay it here rather than when the server admits the frame.
+        for t in (self.pc1, self.prob):
+            t.to("cuda", non_blocking=False)
         self.H, self.W = self.pc1.shape
         self.C = self.prob.shape[2]
         self.K, self.R, self.lam, self.cls = int(K), int(R), float(lam), cls

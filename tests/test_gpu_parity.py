@@ -228,6 +228,35 @@ def test_batch_matches_single_frames_and_oracle(ctx):
             assert_parity(got, oracle.knn_filter(p, q, s.K, s.R, s.lam), f"batch {s}")
 
 
+def test_batch_table_size_boundary(ctx):
+    """Tables of up to 39 work items reach the device as a kernel argument,
+    larger ones through a copy: batches of 38..41 small frames of different
+    shapes, both launch modes, each frame bitwise equal to its own launch."""
+    import torch
+
+    rng = np.random.default_rng(21)
+    for n in (38, 39, 40, 41):
+        specs = [inputs.FrameSpec("unif", int(rng.integers(3, 20)), int(rng.integers(8, 40)), 100 + k,
+                                  K=int(rng.integers(1, 9)), R=int(rng.integers(1, 4)))
+                 for k in range(n)]
+        data = [s.make() for s in specs]
+        singles = [run_gpu(ctx, p, q, s.K, s.R, s.lam, PRU18) for s, (p, q) in zip(specs, data)]
+        for launch in (1, 2):
+            plan = dict(PRU18, launch=launch)
+            say(f"batch of {n} frames, launch mode {launch}")
+            batch = [DeviceFrame(p, q, s.K, s.R, s.lam) for s, (p, q) in zip(specs, data)]
+            for df in batch:
+                df.clear_outputs()
+            _lib.knnf_filter_batch(ctx, [df.as_c() for df in batch], plan, current_stream())
+            torch.cuda.synchronize()
+            for k, df in enumerate(batch):
+                for x, y in zip(df.results(), singles[k]):
+                    assert np.array_equal(x, y), f"batch of {n}, frame {k}, launch {launch}"
+        for k in (0, n - 1):
+            s, (p, q) = specs[k], data[k]
+            assert_parity(singles[k], oracle.knn_filter(p, q, s.K, s.R, s.lam), f"frame {k}")
+
+
 def test_invalid_frame_is_rejected_before_launch(ctx):
     pc1, prob = inputs.g_unif(4, 4, 0)
     df = DeviceFrame(pc1, prob, 9, 0, 0.01)  # K = 9 > window of 4
