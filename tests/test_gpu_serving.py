@@ -148,3 +148,50 @@ def test_server_pool_must_be_aligned(ctx):
         assert ei.value.status == _lib.KNNF_EINVAL
     h = _lib.knnf_server_create(ctx, pool.data_ptr(), 1 << 20)
     _lib.knnf_server_destroy(h)
+
+
+class _PageableFrame:
+    """A host frame in ordinary (pageable) numpy memory: the server copies it
+    with the copy engine, never with the copy kernel."""
+
+    def __init__(self, pc1, prob, K, R, lam):
+        self.pc1 = np.ascontiguousarray(pc1, np.float32)
+        self.prob = np.ascontiguousarray(prob, np.float32)
+        self.H, self.W = self.pc1.shape
+        self.C = self.prob.shape[2]
+        self.K, self.R, self.lam = K, R, lam
+
+    def as_c(self, t_arrival=-1.0, with_nbr=False):
+        f = _lib.knnf_host_frame()
+        f.H, f.W, f.C, f.K, f.R, f.lam = self.H, self.W, self.C, self.K, self.R, self.lam
+        f.pc1 = self.pc1.ctypes.data
+        f.prob = self.prob.ctypes.data
+        f.with_nbr = 0
+        f.t_arrival = t_arrival
+        return f
+
+
+@pytest.mark.parametrize("mode", [_lib.KNNF_SERVE_BATCHED, _lib.KNNF_SERVE_PLAIN], ids=["batched", "plain"])
+def test_burst_through_the_copier(ctx, mode):
+    """80 frames submitted together back up the copy stream, so most of them
+    are copied by the copier thread, the small ones in pinned memory by the
+    copy kernel; pageable frames in the burst take the copy engine.  Every
+    frame equals the frame filtered alone."""
+    specs = ([inputs.FrameSpec("derma", 50, 50, 200 + k, K=16, R=7) for k in range(60)]
+             + [inputs.FrameSpec("brain", 120, 160, 300 + k, K=40, R=14) for k in range(12)]
+             + [inputs.FrameSpec("derma", 300, 260, 400 + k, K=40, R=14) for k in range(4)]
+             + [inputs.FrameSpec("unif", 40, 70, 500 + k, K=8, R=4) for k in range(4)])
+    order = np.random.default_rng(3).permutation(len(specs))
+    specs = [specs[i] for i in order]
+    data = [s.make() for s in specs]
+    frames = [(_PageableFrame if s.gen == "unif" else HostFrame)(p, q, s.K, s.R, s.lam)
+              for s, (p, q) in zip(specs, data)]
+    say(f"burst of {len(frames)} frames, mode {mode}")
+    with Server(ctx, 256 << 20, mode=mode) as srv:
+        results = {}
+        replay(srv, frames, [0.0] * len(frames),
+               keep=lambda k, v: results.__setitem__(k, srv.view_arrays(v)))
+    for k, (s, d) in enumerate(zip(specs, data)):
+        alone = _alone(ctx, s, d)
+        assert np.array_equal(results[k][1], alone[1]), f"class differs for frame {k} ({s})"
+        assert np.array_equal(results[k][0], alone[0]), f"prob differs for frame {k} ({s})"
