@@ -582,23 +582,40 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
         // its bottom edge), so all E loads are in flight together.
         uint32_t x[E];
         float pv[E];
+        if (E == 8 && W >= 8 && !ballot(lbr != 3)) {
+            // every block is 8 x 8 (P = 8): element u * 8 + lp is row rb + u,
+            // column cb + lp < W, so a lane's column term is computed once
+            const int j = cb + lp;
+            const uint32_t o = (uint32_t)rb * (uint32_t)W + (uint32_t)j;
 #pragma unroll
-        for (int u = 0; u < E; ++u) {
-            const int e = u * P + lp;
-            const int i = rb + (e >> lbc);
-            const int j = min(cb + (e & (bc - 1)), W - 1);
-            pv[u] = pc1[(uint32_t)i * (uint32_t)W + (uint32_t)j];
-        }
-#pragma unroll
-        for (int u = 0; u < E; ++u) {
-            const int e = u * P + lp;
-            const int i = rb + (e >> lbc);
-            const int j = cb + (e & (bc - 1));
-            const float a = frq - feat(lam, i);
+            for (int u = 0; u < E; ++u) pv[u] = pc1[o + (uint32_t)u * (uint32_t)W];
             const float b = fcq - feat(lam, j);
-            const float ee = iqs - pv[u];
-            const uint32_t d = __float_as_uint(fmaf(ee, ee, fmaf(b, b, a * a)));
-            x[u] = (sok && j < W) ? d : 0x7f800000u;  // +inf: no candidate
+#pragma unroll
+            for (int u = 0; u < E; ++u) {
+                const float a = frq - feat(lam, rb + u);
+                const float ee = iqs - pv[u];
+                const uint32_t d = __float_as_uint(fmaf(ee, ee, fmaf(b, b, a * a)));
+                x[u] = sok ? d : 0x7f800000u;
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < E; ++u) {
+                const int e = u * P + lp;
+                const int i = rb + (e >> lbc);
+                const int j = min(cb + (e & (bc - 1)), W - 1);
+                pv[u] = pc1[(uint32_t)i * (uint32_t)W + (uint32_t)j];
+            }
+#pragma unroll
+            for (int u = 0; u < E; ++u) {
+                const int e = u * P + lp;
+                const int i = rb + (e >> lbc);
+                const int j = cb + (e & (bc - 1));
+                const float a = frq - feat(lam, i);
+                const float b = fcq - feat(lam, j);
+                const float ee = iqs - pv[u];
+                const uint32_t d = __float_as_uint(fmaf(ee, ee, fmaf(b, b, a * a)));
+                x[u] = (sok && j < W) ? d : 0x7f800000u;  // +inf: no candidate
+            }
         }
         if (lp == 0) S.iq[sq] = iqs;
         seg_sort_u32<E>(x, lp);
