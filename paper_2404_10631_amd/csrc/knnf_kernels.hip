@@ -18,7 +18,7 @@
 // binary32 operation and fmaf is the only fused operation.
 //
 // Work decomposition (not the paper's; designed for 64-wide wavefronts):
-//   * One wavefront task = a tile of QR x QC query pixels (default 2 x 4).
+//   * One wavefront task = a tile of QR x QC query pixels (default 1 x 8).
 //     Per-query state lives in VGPRs and a small per-wavefront LDS block.
 //   * pass A (bound): the 64 candidates of a compact block around each query
 //     (8 rows x 8 columns where the window allows) are evaluated and sorted
