@@ -48,6 +48,7 @@ knnf_status hip_fail(hipError_t e, const char* what) {
 struct BatchSlot {
     void* dev = nullptr;
     void* host = nullptr;
+    void* host_dev = nullptr;  // device address of the pinned staging, if mapped
     size_t cap = 0;           // work items
     hipEvent_t done = nullptr;
     bool recorded = false;
@@ -73,7 +74,7 @@ hipError_t grow_slot(BatchSlot& s, size_t n) {
     while (cap < n) cap *= 2;
     if (s.dev) hipFree(s.dev);
     if (s.host) hipHostFree(s.host);
-    s.dev = s.host = nullptr;
+    s.dev = s.host = s.host_dev = nullptr;
     s.cap = 0;
     hipError_t e = hipMalloc(&s.dev, slot_bytes(cap));
     if (e != hipSuccess) return e;
@@ -82,6 +83,11 @@ hipError_t grow_slot(BatchSlot& s, size_t n) {
         hipFree(s.dev);
         s.dev = nullptr;
         return e;
+    }
+    s.host_dev = nullptr;
+    if (hipHostGetDevicePointer(&s.host_dev, s.host, 0) != hipSuccess) {
+        s.host_dev = nullptr;
+        (void)hipGetLastError();  // not mapped: the table is copied instead
     }
     s.cap = cap;
     return hipSuccess;
@@ -289,9 +295,18 @@ knnf_status launch_items(knnf_ctx* ctx, const WorkItem* items, int n, const knnf
             acc += items[k].ntiles;
         }
         hts[n] = acc;
-        // one copy of the whole table prefix: descriptors, prefix, first tiles
-        e = hipMemcpyAsync(s.dev, s.host, off_counter(s.cap), hipMemcpyHostToDevice, hs);
-        if (e != hipSuccess) return hip_fail(e, "batch table copy");
+        // the whole table prefix (descriptors, prefix, first tiles) goes to the
+        // device in one piece: pulled by a kernel from the mapped staging (a
+        // copy call could hold this thread for milliseconds), else copied
+        if (s.host_dev) {
+            const int rc = knnf::launch_copy_pair((const uint32_t*)s.host_dev, (uint32_t*)s.dev,
+                                                  (uint32_t)(off_counter(s.cap) / 4), nullptr,
+                                                  nullptr, 0, stream);
+            if (rc != 0) return hip_fail((hipError_t)rc, "batch table write");
+        } else {
+            e = hipMemcpyAsync(s.dev, s.host, off_counter(s.cap), hipMemcpyHostToDevice, hs);
+            if (e != hipSuccess) return hip_fail(e, "batch table copy");
+        }
     }
     uint32_t* d_ctr = (uint32_t*)((char*)s.dev + off_counter(s.cap));
     const knnf::LaunchCfg cfg = to_cfg(p);
