@@ -138,12 +138,15 @@ struct knnf_server {
 
 namespace {
 
-// When the copy stream is backed up, inputs of at most this many bytes that
-// sit in pinned, device-mapped host memory are copied by a kernel on the copy
+// In batched mode, while the copy stream is backed up, inputs that sit in
+// pinned, device-mapped host memory are copied by a kernel on the copy
 // stream: a host-to-device copy call then sometimes held its thread for
-// 7-11 ms, and every frame queued behind it waited as long.  An idle copy
-// stream, and larger inputs, keep the copy engine, which is faster.
-constexpr size_t kKernelCopyMax = 4u << 20;
+// 7-11 ms, and every frame queued behind it waited as long.  A kernel reads
+// mapped host memory as fast as the copy engine (57 GB/s); an idle copy
+// stream keeps the copy engine, whose latency is lower.  The plain baseline
+// always uses the copy engine.  (Bound: the copy kernel counts words in 32
+// bits.)
+constexpr size_t kKernelCopyMax = 1u << 30;
 
 // Device address of pinned host memory at p, or null if the runtime does not
 // report p as device-mapped host memory.
@@ -486,7 +489,8 @@ knnf_status knnf_server_submit(knnf_server* s, const knnf_host_frame* f, uint64_
     const size_t bytes = knnf_frame_bytes(f->H, f->W, f->C, f->K, f->with_nbr ? 1 : 0);
     const void* m1 = nullptr;
     const void* m2 = nullptr;
-    if ((size_t)f->H * (size_t)f->W * (size_t)(f->C + 1) * 4 <= kKernelCopyMax) {
+    if (s->opts.mode == KNNF_SERVE_BATCHED &&
+        (size_t)f->H * (size_t)f->W * (size_t)(f->C + 1) * 4 <= kKernelCopyMax) {
         m1 = device_view(f->pc1);
         m2 = device_view(f->prob);
         if (!m1 || !m2) m1 = m2 = nullptr;

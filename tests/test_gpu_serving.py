@@ -174,9 +174,9 @@ class _PageableFrame:
 @pytest.mark.parametrize("mode", [_lib.KNNF_SERVE_BATCHED, _lib.KNNF_SERVE_PLAIN], ids=["batched", "plain"])
 def test_burst_through_the_copier(ctx, mode):
     """80 frames submitted together back up the copy stream, so most of them
-    are copied by the copier thread, the small ones in pinned memory by the
-    copy kernel; pageable frames in the burst take the copy engine.  Every
-    frame equals the frame filtered alone."""
+    are copied by the copier thread, in batched mode those in pinned memory
+    by the copy kernel; pageable frames (and the plain mode) take the copy
+    engine.  Every frame equals the frame filtered alone."""
     specs = ([inputs.FrameSpec("derma", 50, 50, 200 + k, K=16, R=7) for k in range(60)]
              + [inputs.FrameSpec("brain", 120, 160, 300 + k, K=40, R=14) for k in range(12)]
              + [inputs.FrameSpec("derma", 300, 260, 400 + k, K=40, R=14) for k in range(4)]
