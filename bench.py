@@ -202,10 +202,11 @@ def batch_leg(ctx, plan, stream, reps=3):
     for wl in (inputs.config2(), inputs.config3()):
         frames = [DeviceFrame(*f.make(), f.K, f.R, f.lam, with_nbr=False) for f in wl.frames]
         cfs = [f.as_c() for f in frames]
+        arr = _lib.frame_array(cfs)  # the C frame table, built once as a C caller would
         # the batched schedule (search, tile shape, waves, launch mode) is
         # picked by the library's autotuner on these frames
-        tuned = _lib.knnf_tune(ctx, cfs, 2, stream).as_dict()
-        t_batch = time_gpu(lambda: _lib.knnf_filter_batch(ctx, cfs, tuned, stream), reps)
+        tuned = _lib.knnf_tune(ctx, arr, 2, stream).as_dict()
+        t_batch = time_gpu(lambda: _lib.knnf_filter_batch(ctx, arr, tuned, stream), reps)
 
         def plain():
             for c in cfs:

@@ -200,15 +200,27 @@ def knnf_filter(ctx: int, frame: knnf_frame, plan=None, stream: int = 0) -> None
     check(load().knnf_filter(ctx, ctypes.byref(frame), _plan_ptr(plan), stream))
 
 
+def frame_array(frames):
+    """A C array of knnf_frame, built once for repeated batched calls over
+    the same frames (building it costs ~0.1-0.2 us per frame in Python)."""
+    return (knnf_frame * len(frames))(*frames)
+
+
+def _frames_arg(frames):
+    arr = frames if isinstance(frames, ctypes.Array) else frame_array(frames)
+    return arr, len(arr)
+
+
 def knnf_filter_batch(ctx: int, frames, plan=None, stream: int = 0) -> None:
-    arr = (knnf_frame * len(frames))(*frames)
-    check(load().knnf_filter_batch(ctx, arr, len(frames), _plan_ptr(plan), stream))
+    """frames: a list of knnf_frame or an array from frame_array()."""
+    arr, n = _frames_arg(frames)
+    check(load().knnf_filter_batch(ctx, arr, n, _plan_ptr(plan), stream))
 
 
 def knnf_tune(ctx: int, frames, reps: int = 3, stream: int = 0) -> knnf_plan:
-    arr = (knnf_frame * len(frames))(*frames)
+    arr, n = _frames_arg(frames)
     best = knnf_plan()
-    check(load().knnf_tune(ctx, arr, len(frames), int(reps), stream, ctypes.byref(best)))
+    check(load().knnf_tune(ctx, arr, n, int(reps), stream, ctypes.byref(best)))
     return best
 
 
