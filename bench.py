@@ -46,11 +46,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
-    ap.add_argument("--legs", default="plain,batch,serve,pc1,variants",
+    ap.add_argument("--legs", default="plain,batch,serve,pc1,svm,variants",
                     help="comma list of: plain (headline), batch (uneven / small-frame "
                          "batches), serve (Poisson mixed stream), pc1 (the projection "
-                         "step that produces the band), variants (whole-frame window, "
-                         "lambda = 0)")
+                         "step that produces the band), svm (the probability maps), "
+                         "variants (whole-frame window, lambda = 0)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (to scale HBM counters)")
     ap.add_argument("--serve-frames", type=int, default=2000)
@@ -191,6 +191,54 @@ def pc1_leg(ctx, stream, reps=20):
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
                          "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
                          "traffic": (rec or {}).get("traffic_bytes_per_call")}}
+
+
+def svm_leg(ctx, stream, reps=20):
+    """SVM probability maps (one-vs-one, four classes) of a brain-like cube
+    (W480 x H380, 128 bands) and of a dermatology-like one (1000 x 1000, 100
+    bands) on the device, one launch each, HBM-bound."""
+    import torch
+
+    from paper_2404_10631_amd import _lib, inputs
+
+    out = {}
+    for key, (H, W, B, kind) in (("brain", (380, 480, 128, "brain")),
+                                 ("derma", (1000, 1000, 100, "derma"))):
+        cube, _, _ = inputs.g_cube(H, W, B, 1, kind)
+        model = [torch.from_numpy(a).cuda() for a in inputs.g_svm_model(4, B, 2)]
+        dcube = torch.from_numpy(cube).cuda()
+        npix = H * W
+        res = torch.empty((npix, 4), dtype=torch.float32, device="cuda")
+        del cube
+
+        def run():
+            _lib.knnf_svm(ctx, dcube.data_ptr(), npix, B, 4, *(t.data_ptr() for t in model),
+                          res.data_ptr(), stream)
+
+        run()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()  # on torch's current stream, the one the launches use
+        for _ in range(reps):
+            run()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        # algorithmic bytes: the cube once, the maps written, the model once
+        nbytes = npix * B * 4 + npix * 4 * 4 + 6 * (B + 3) * 8
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        out[key] = {"workload": f"{kind}-like cube W{W}xH{H}, {B} bands, 4 classes",
+                    "ms": round(ms, 5), "pixels_per_s": round(npix / (ms * 1e-3), 1),
+                    "bytes": nbytes, "GB_per_s": round(gbs, 1)}
+        del dcube, res
+    b = out["brain"]
+    rec = profile_record("svm_prob_brain480x380x128.md", "knnf_svm.hip")
+    gbs = b["GB_per_s"]
+    out["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                       "frac": round(gbs / PEAK_HBM_GBS, 4),
+                       "traffic": (rec or {}).get("traffic_bytes_per_call")}
+    return out
 
 
 def batch_leg(ctx, plan, stream, reps=3):
@@ -418,6 +466,9 @@ def main():
     if "pc1" in legs:
         print("bench: pc1 leg", file=sys.stderr, flush=True)
         out["pc1_projection"] = pc1_leg(ctx, stream)
+    if "svm" in legs:
+        print("bench: svm leg", file=sys.stderr, flush=True)
+        out["svm_probabilities"] = svm_leg(ctx, stream)
     if not args.no_cpu:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(spec, pc1, prob, args.cpu_seconds)

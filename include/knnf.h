@@ -323,6 +323,42 @@ knnf_status knnf_pc1(knnf_ctx* ctx, const float* cube, int64_t npix, int32_t ban
                      const double* mean, const double* vec, float* out, int32_t normalize,
                      void* stream);
 
+/* ---- SVM probabilities: the maps the filter averages ---------------------
+ *
+ * The classification stage of the one-vs-one SVM of Sec. II.C.1 (GPU
+ * versions Sec. III.A.1, III.B.1), per pixel x: decision values against every
+ * binary hyperplane, their binary probabilities through a sigmoid, and the
+ * multiclass probabilities by pairwise coupling (the second method of the
+ * paper's reference [30], Wu, Lin and Weng).  Training is offline and not
+ * part of the library: the model is an input.
+ *
+ *   f[m] = sum_b w[m][b] x[b] + bias[m]                       binary64
+ *   r[m] = 1 / (1 + exp(A[m] f[m] + B[m])), clamped to [1e-7, 1 - 1e-7]
+ *          (class i of the pair; 1 - r[m] for class j)
+ *   Q[t][t] = sum_{s != t} r_st^2,  Q[t][j] = -r_jt r_tj
+ *   p = uniform; sweep t = 0..C-1: p[t] <- (p'Qp - sum_{j != t} Q[t][j] p[j]) / Q[t][t],
+ *          then p /= sum(p); until max_t |(Qp)[t] - p'Qp| < 0.005 / C, at most 100 sweeps
+ *   out[p][c] = p[c] rounded once to binary32
+ *
+ * Hyperplane m covers the class pair (i, j), i < j, in lexicographic order
+ * (0,1), (0,2), ..., (0,C-1), (1,2), ...; M = C (C - 1) / 2.
+ * cube     device, npix x bands float32, pixel-major (a pixel's bands contiguous)
+ * w        device, M x bands float64 (hyperplanes, row m = pair m)
+ * bias, A, B  device, M float64 each (offsets and sigmoid parameters)
+ * out      device, npix x classes float32, class fastest; may be the prob
+ *          buffer of a knnf_frame
+ * Asynchronous on `stream`; no workspace, no allocation.
+ * Errors: KNNF_EINVAL for a NULL argument, npix outside [1, 2^31], bands
+ * outside [1, KNNF_SVM_MAX_BANDS], classes outside [2, KNNF_SVM_MAX_CLASSES];
+ * KNNF_EDEVICE for a failed launch.
+ */
+#define KNNF_SVM_MAX_CLASSES 8
+#define KNNF_SVM_MAX_BANDS 4096
+#define KNNF_SVM_MAX_PIXELS (1LL << 31)
+knnf_status knnf_svm(knnf_ctx* ctx, const float* cube, int64_t npix, int32_t bands,
+                     int32_t classes, const double* w, const double* bias, const double* A,
+                     const double* B, float* out, void* stream);
+
 /* Text of the last error on the calling thread ("" if none). */
 const char* knnf_last_error(void);
 

@@ -31,9 +31,9 @@ Readings where the paper is silent (each stated again where it is used):
 * the iteration stops when max_t |(Q p)[t] - p^T Q p| < 0.005 / C (the
   optimality condition of the coupling problem, within a tolerance) or after
   100 sweeps -- the paper names a threshold and a maximum without values;
-* every step is evaluated in binary64 (hyperplanes and image are binary32;
-  their products are exact in binary64), and the probabilities are rounded
-  once to binary32 at the end, class fastest -- the layout the filter reads.
+* every step is evaluated in binary64 (the image is binary32, the model
+  binary64), and the probabilities are rounded once to binary32 at the end,
+  class fastest -- the layout the filter reads.
 
 Pinned by ``tests/test_svm_oracle_pins.py``: exact rational decision values on
 tiny cubes, the sigmoid's special values, consistent pairwise probabilities
@@ -57,7 +57,7 @@ def pairs(C: int):
 def decision(cube, w, bias) -> np.ndarray:
     """Step (i): f[p][m] = sum_b w[m][b] * x[p][b] + bias[m] in binary64, [P, M]."""
     x = np.asarray(cube, dtype=np.float32).astype(np.float64)
-    wm = np.asarray(w, dtype=np.float32).astype(np.float64)
+    wm = np.asarray(w, dtype=np.float64)
     b = np.asarray(bias, dtype=np.float64)
     if x.ndim != 2 or wm.ndim != 2 or wm.shape[1] != x.shape[1] or b.shape != (wm.shape[0],):
         raise ValueError("cube [P, B], w [M, B], bias [M]")

@@ -125,6 +125,8 @@ _SIGS = {
     "knnf_server_destroy": (_I, [_P]),
     "knnf_version": (ctypes.c_char_p, []),
     "knnf_pc1": (_I, [_P, _P, ctypes.c_int64, ctypes.c_int32, _P, _P, _P, ctypes.c_int32, _P]),
+    "knnf_svm": (_I, [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P,
+                      _P]),
 }
 
 _lib = None
@@ -287,3 +289,10 @@ def knnf_pc1(ctx: int, cube_ptr: int, npix: int, bands: int, mean_ptr: int, vec_
     """PC1 projection of a device cube (see include/knnf.h); device pointers."""
     check(load().knnf_pc1(ctx, cube_ptr, int(npix), int(bands), mean_ptr, vec_ptr, out_ptr,
                           1 if normalize else 0, stream))
+
+
+def knnf_svm(ctx: int, cube_ptr: int, npix: int, bands: int, classes: int, w_ptr: int,
+             bias_ptr: int, a_ptr: int, b_ptr: int, out_ptr: int, stream: int = 0) -> None:
+    """SVM probability maps of a device cube (see include/knnf.h); device pointers."""
+    check(load().knnf_svm(ctx, cube_ptr, int(npix), int(bands), int(classes), w_ptr, bias_ptr,
+                          a_ptr, b_ptr, out_ptr, stream))

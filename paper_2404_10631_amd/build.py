@@ -23,7 +23,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libknnf.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["knnf_kernels.hip", "knnf_pc1.hip", "knnf_api.cpp", "knnf_server.cpp"]
+SOURCES = ["knnf_kernels.hip", "knnf_pc1.hip", "knnf_svm.hip", "knnf_api.cpp", "knnf_server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("KNNF_OFFLOAD_ARCH", "gfx950")

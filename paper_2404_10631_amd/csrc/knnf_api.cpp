@@ -511,6 +511,30 @@ knnf_status knnf_pc1(knnf_ctx* ctx, const float* cube, int64_t npix, int32_t ban
     return KNNF_OK;
 }
 
+knnf_status knnf_svm(knnf_ctx* ctx, const float* cube, int64_t npix, int32_t bands,
+                     int32_t classes, const double* w, const double* bias, const double* A,
+                     const double* B, float* out, void* stream) {
+    if (npix < 1 || npix > KNNF_SVM_MAX_PIXELS)
+        return fail(KNNF_EINVAL, "knnf_svm: npix %lld outside [1, 2^31]", (long long)npix);
+    if (bands < 1 || bands > KNNF_SVM_MAX_BANDS)
+        return fail(KNNF_EINVAL, "knnf_svm: bands %d outside [1, %d]", bands, KNNF_SVM_MAX_BANDS);
+    if (classes < 2 || classes > KNNF_SVM_MAX_CLASSES)
+        return fail(KNNF_EINVAL, "knnf_svm: classes %d outside [2, %d]", classes,
+                    KNNF_SVM_MAX_CLASSES);
+    if (!cube || !w || !bias || !A || !B || !out) return fail(KNNF_EINVAL, "knnf_svm: NULL pointer");
+    if (!ctx) return fail(KNNF_EINVAL, "knnf_svm: NULL context");
+    int prev = 0;
+    hipGetDevice(&prev);
+    if (prev != ctx->device) hipSetDevice(ctx->device);
+    struct Restore {
+        int prev, dev;
+        ~Restore() { if (prev != dev) hipSetDevice(prev); }
+    } restore{prev, ctx->device};
+    const int rc = knnf::launch_svm(cube, npix, bands, classes, w, bias, A, B, out, stream);
+    if (rc != 0) return hip_fail((hipError_t)rc, "knnf_svm launch");
+    return KNNF_OK;
+}
+
 knnf_status knnf_stats_enable(knnf_ctx* ctx, int on) {
     if (!ctx) return fail(KNNF_EINVAL, "knnf_stats_enable: NULL context");
     if (on && !ctx->d_stats) {

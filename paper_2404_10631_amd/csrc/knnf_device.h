@@ -72,4 +72,8 @@ int pc1_max_blocks();
 int launch_pc1(const float* cube, int64_t npix, int bands, const double* mean, const double* vec,
                float* out, double* ws, double* pairs, int num_cu, void* stream);
 
+// SVM probability stage (defined in knnf_svm.hip), 2 <= classes <= 8.
+int launch_svm(const float* cube, int64_t npix, int bands, int classes, const double* w,
+               const double* bias, const double* A, const double* B, float* out, void* stream);
+
 }  // namespace knnf

@@ -1,0 +1,230 @@
+// knnf_svm.hip -- the SVM probability stage (the pixel-wise classifier whose
+// probability maps the KNN filter averages), for CDNA4 (gfx950).
+//
+// Method (one-vs-one SVM, classification stage, Sec. II.C.1; GPU versions
+// Sec. III.A.1 and III.B.1), per pixel x (a spectrum of `bands` values):
+//   (i)   f[m] = sum_b w[m][b] x[b] + bias[m]  for every hyperplane m, one per
+//         class pair (i, j), i < j, in lexicographic order;
+//   (ii)  r[m] = 1 / (1 + exp(A[m] f[m] + B[m])), clamped to [1e-7, 1 - 1e-7]:
+//         the probability of class i within the pair, 1 - r[m] that of j;
+//   (iii) pairwise coupling (the second method of Wu, Lin and Weng, cited as
+//         [30]): with Q[t][t] = sum_{s != t} r_st^2 and Q[t][j] = -r_jt r_tj,
+//         sweep p[t] <- (p^T Q p - sum_{j != t} Q[t][j] p[j]) / Q[t][t], each
+//         update followed by renormalising p, from the uniform p, until
+//         max_t |(Q p)[t] - p^T Q p| < 0.005 / C or 100 sweeps.
+// Every step is binary64; the probabilities are rounded once to binary32,
+// pixel-major with the class fastest (the layout the filter reads).
+//
+// Work shape: the cube is read once (4 B per pixel and band) and everything
+// else is per-pixel arithmetic, so the kernel is HBM-bound.  A block owns 256
+// consecutive pixels.  It stages the cube through LDS in chunks of 32 bands:
+// eight lanes cover one pixel's 128-byte piece of the chunk with 16-byte
+// loads, so every cache line that a load touches is used whole.  Then each
+// lane owns one pixel for the dot products (hyperplane weights at
+// wave-uniform addresses, i.e. scalar loads) and for the coupling iteration,
+// whose sweep count differs from pixel to pixel.  The loads of the next
+// chunk are in flight while the current one is used, so every wave keeps
+// HBM requests outstanding through its dot products.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "knnf_device.h"
+
+namespace knnf {
+namespace {
+
+constexpr int SVM_THREADS = 256;              // pixels per block
+constexpr int SVM_CHUNK = 32;                 // bands per LDS stage
+constexpr int SVM_STRIDE = SVM_CHUNK + 4;     // LDS row stride (floats): conflict-free 16-byte reads
+constexpr int SVM_SWEEPS = 100;
+constexpr double SVM_CLAMP = 1e-7;
+
+// Hyperplane of the pair (i, j), i < j, in the order (0,1), (0,2), ..., (C-2,C-1).
+template <int C>
+__device__ __forceinline__ constexpr int pair_index(int i, int j) {
+    return i * C - i * (i + 1) / 2 + (j - i - 1);
+}
+
+template <int C, bool VEC>
+__global__ void __launch_bounds__(SVM_THREADS)
+svm_prob_kernel(const float* __restrict__ cube, int64_t npix, int bands,
+                const double* __restrict__ w, const double* __restrict__ bias,
+                const double* __restrict__ A, const double* __restrict__ B,
+                float* __restrict__ out) {
+    constexpr int M = C * (C - 1) / 2;
+    __shared__ __attribute__((aligned(16))) float tile[SVM_THREADS * SVM_STRIDE];
+    const int tid = threadIdx.x;
+    const int64_t first = (int64_t)blockIdx.x * SVM_THREADS;
+    const int64_t last = npix - 1;
+
+    // (i) decision values, accumulated band by band in ascending order
+    double f[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) f[m] = 0.0;
+    const float* row = tile + tid * SVM_STRIDE;
+    // Staging of cube[first .. first+255][c0 .. c0+31] (rows past the frame
+    // repeat its last pixel, bands past the cube read as 0).  The next chunk
+    // is loaded into registers while the current one is used from LDS.
+    // 16-byte path: lane (q, r0) loads column 4q of rows r0, r0 + 32, ...
+    // Scalar path: lane (q, r0) loads band q of rows r0, r0 + 8, ...
+    constexpr int NLOAD = VEC ? 8 : 32;
+    using Piece = typename std::conditional<VEC, float4, float>::type;
+    Piece v[NLOAD];
+    const int q = VEC ? (tid & 7) : (tid & 31);
+    const int r0 = VEC ? (tid >> 3) : (tid >> 5);
+    constexpr int RSTEP = VEC ? 32 : 8;
+    auto fetch = [&](int c0) {
+        const int b = c0 + (VEC ? 4 * q : q);
+#pragma unroll
+        for (int i = 0; i < NLOAD; ++i) {
+            int64_t p = first + r0 + RSTEP * i;
+            p = p < npix ? p : last;
+            if constexpr (VEC)
+                v[i] = b < bands ? *(const float4*)(cube + p * (int64_t)bands + b)
+                                 : make_float4(0.f, 0.f, 0.f, 0.f);
+            else
+                v[i] = b < bands ? cube[p * (int64_t)bands + b] : 0.f;
+        }
+    };
+    fetch(0);
+    for (int c0 = 0; c0 < bands; c0 += SVM_CHUNK) {
+#pragma unroll
+        for (int i = 0; i < NLOAD; ++i) {
+            if constexpr (VEC)
+                *(float4*)(tile + (r0 + RSTEP * i) * SVM_STRIDE + 4 * q) = v[i];
+            else
+                tile[(r0 + RSTEP * i) * SVM_STRIDE + q] = v[i];
+        }
+        __syncthreads();
+        if (c0 + SVM_CHUNK < bands) fetch(c0 + SVM_CHUNK);
+        const double* wc = w + c0;
+        if (c0 + SVM_CHUNK <= bands) {
+#pragma unroll
+            for (int k = 0; k < SVM_CHUNK / 4; ++k) {
+                const float4 x4 = *(const float4*)(row + 4 * k);
+                const double x[4] = {(double)x4.x, (double)x4.y, (double)x4.z, (double)x4.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+#pragma unroll
+                    for (int m = 0; m < M; ++m)
+                        f[m] = fma(wc[(int64_t)m * bands + 4 * k + e], x[e], f[m]);
+            }
+        } else {
+            const int nb = bands - c0;
+            for (int k = 0; k < nb; ++k) {
+                const double x = (double)row[k];
+#pragma unroll
+                for (int m = 0; m < M; ++m) f[m] = fma(wc[(int64_t)m * bands + k], x, f[m]);
+            }
+        }
+        __syncthreads();
+    }
+    const int64_t pix = first + tid;
+    if (pix >= npix) return;
+
+    // (ii) binary probabilities; r[m] is that of the pair's first class
+    double r[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const double z = (f[m] + bias[m]) * A[m] + B[m];
+        const double s = 1.0 / (1.0 + exp(z));
+        r[m] = fmin(fmax(s, SVM_CLAMP), 1.0 - SVM_CLAMP);
+    }
+    // (iii) coupling.  Q[t][t] sums r_st^2 over s in ascending order;
+    // the off-diagonal Q[t][j] = -r_jt r_tj is the same for (t, j) and (j, t).
+    double qtt[C];
+#pragma unroll
+    for (int t = 0; t < C; ++t) {
+        double s = 0.0;
+#pragma unroll
+        for (int u = 0; u < C; ++u) {
+            if (u == t) continue;
+            const double rut = u < t ? r[pair_index<C>(u, t)] : 1.0 - r[pair_index<C>(t, u)];
+            s = s + rut * rut;
+        }
+        qtt[t] = s;
+    }
+    double qo[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) qo[m] = -((1.0 - r[m]) * r[m]);
+    auto Q = [&](int t, int j) -> double {
+        return t == j ? qtt[t] : t < j ? qo[pair_index<C>(t, j)] : qo[pair_index<C>(j, t)];
+    };
+
+    // The sweep keeps Q p and p^T Q p up to date instead of recomputing
+    // them: the new p[t] equals p[t] + d with d = (p^T Q p - (Q p)[t]) / Q[t][t];
+    // before renormalising, Q p gains d times column t of Q and p^T Q p gains
+    // 2 d (Q p)[t] + d^2 Q[t][t]; renormalising divides p and Q p by 1 + d
+    // (the sum of p before it) and p^T Q p by its square.  Same fixed-point
+    // step as the plain form, O(C) per update instead of O(C^2).
+    double p[C], qp[C], rq[C];
+#pragma unroll
+    for (int t = 0; t < C; ++t) {
+        p[t] = 1.0 / C;
+        rq[t] = 1.0 / qtt[t];
+    }
+    double pqp = 0.0;
+#pragma unroll
+    for (int t = 0; t < C; ++t) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < C; ++j) s = fma(Q(t, j), p[j], s);
+        qp[t] = s;
+        pqp = fma(p[t], s, pqp);
+    }
+    const double eps = 0.005 / C;
+    for (int sweep = 0; sweep < SVM_SWEEPS; ++sweep) {
+        double err = 0.0;
+#pragma unroll
+        for (int t = 0; t < C; ++t) err = fmax(err, fabs(qp[t] - pqp));
+        if (!(err >= eps)) break;
+#pragma unroll
+        for (int t = 0; t < C; ++t) {
+            const double d = (pqp - qp[t]) * rq[t];
+            const double inv = 1.0 / (1.0 + d);
+            pqp = fma(d, fma(d, qtt[t], 2.0 * qp[t]), pqp) * inv * inv;
+#pragma unroll
+            for (int j = 0; j < C; ++j) qp[j] = fma(d, Q(j, t), qp[j]) * inv;
+            p[t] += d;
+#pragma unroll
+            for (int j = 0; j < C; ++j) p[j] *= inv;
+        }
+    }
+    float* o = out + pix * C;
+#pragma unroll
+    for (int t = 0; t < C; ++t) o[t] = (float)p[t];
+}
+
+template <int C>
+int launch_c(const float* cube, int64_t npix, int bands, const double* w, const double* bias,
+             const double* A, const double* B, float* out, void* stream) {
+    const int64_t blocks = (npix + SVM_THREADS - 1) / SVM_THREADS;
+    const bool vec = bands % 4 == 0 && ((uintptr_t)cube & 15) == 0;
+    if (vec)
+        hipLaunchKernelGGL((svm_prob_kernel<C, true>), dim3((uint32_t)blocks), dim3(SVM_THREADS), 0,
+                           (hipStream_t)stream, cube, npix, bands, w, bias, A, B, out);
+    else
+        hipLaunchKernelGGL((svm_prob_kernel<C, false>), dim3((uint32_t)blocks), dim3(SVM_THREADS), 0,
+                           (hipStream_t)stream, cube, npix, bands, w, bias, A, B, out);
+    return (int)hipGetLastError();
+}
+
+}  // namespace
+
+int launch_svm(const float* cube, int64_t npix, int bands, int classes, const double* w,
+               const double* bias, const double* A, const double* B, float* out, void* stream) {
+    switch (classes) {
+        case 2: return launch_c<2>(cube, npix, bands, w, bias, A, B, out, stream);
+        case 3: return launch_c<3>(cube, npix, bands, w, bias, A, B, out, stream);
+        case 4: return launch_c<4>(cube, npix, bands, w, bias, A, B, out, stream);
+        case 5: return launch_c<5>(cube, npix, bands, w, bias, A, B, out, stream);
+        case 6: return launch_c<6>(cube, npix, bands, w, bias, A, B, out, stream);
+        case 7: return launch_c<7>(cube, npix, bands, w, bias, A, B, out, stream);
+        case 8: return launch_c<8>(cube, npix, bands, w, bias, A, B, out, stream);
+        default: return (int)hipErrorInvalidValue;
+    }
+}
+
+}  // namespace knnf

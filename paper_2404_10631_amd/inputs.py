@@ -154,18 +154,18 @@ def g_svm_model(C: int, B: int, seed: int):
     """A synthetic one-vs-one SVM model for the probability stage (the
     paper's trained models are not available): for every class pair (i, j),
     i < j, in lexicographic order, a hyperplane w ~ N(0, 1) * 40 / sqrt(B)
-    (binary32), an offset that centres it on a flat 0.35 reflectance plus
+    (binary64), an offset that centres it on a flat 0.35 reflectance plus
     N(0, 0.5), and sigmoid parameters A ~ U[-2.5, -0.5], B ~ U[-0.3, 0.3].
     On ``g_cube`` cubes the decision values span a few units, so the binary
     probabilities cover (0, 1) and the coupling runs several sweeps.
 
-    Returns ``w`` float32 [M, B], ``bias``, ``A``, ``B`` float64 [M],
+    Returns ``w`` float64 [M, B], ``bias``, ``A``, ``B`` float64 [M],
     M = C (C - 1) / 2.
     """
     rng = np.random.default_rng(seed)
     M = C * (C - 1) // 2
-    w = (rng.normal(0.0, 1.0, (M, B)) * (40.0 / np.sqrt(B))).astype(np.float32)
-    bias = -0.35 * w.astype(np.float64).sum(axis=1) + rng.normal(0.0, 0.5, M)
+    w = rng.normal(0.0, 1.0, (M, B)) * (40.0 / np.sqrt(B))
+    bias = -0.35 * w.sum(axis=1) + rng.normal(0.0, 0.5, M)
     A = rng.uniform(-2.5, -0.5, M)
     Bp = rng.uniform(-0.3, 0.3, M)
     return (np.ascontiguousarray(w), np.ascontiguousarray(bias), np.ascontiguousarray(A),

@@ -100,3 +100,21 @@ def test_pc1_validation(lib, kw, word):
     st = lib.knnf_pc1(None, a["cube"], a["npix"], a["bands"], a["mean"], a["vec"], a["out"], 1, None)
     assert st == _lib.KNNF_EINVAL
     assert word in _lib.last_error()
+
+
+@pytest.mark.parametrize("kw,word", [
+    (dict(npix=0), "npix"), (dict(npix=(1 << 31) + 1), "npix"),
+    (dict(bands=0), "bands"), (dict(bands=4097), "bands"),
+    (dict(classes=1), "classes"), (dict(classes=9), "classes"),
+    (dict(cube=None), "NULL"), (dict(w=None), "NULL"), (dict(bias=None), "NULL"),
+    (dict(A=None), "NULL"), (dict(B=None), "NULL"), (dict(out=None), "NULL"),
+    (dict(), "context"),
+])
+def test_svm_validation(lib, kw, word):
+    a = dict(cube=0x1000, npix=100, bands=128, classes=4, w=0x2000, bias=0x3000, A=0x4000,
+             B=0x5000, out=0x6000)
+    a.update(kw)
+    st = lib.knnf_svm(None, a["cube"], a["npix"], a["bands"], a["classes"], a["w"], a["bias"],
+                      a["A"], a["B"], a["out"], None)
+    assert st == _lib.KNNF_EINVAL
+    assert word in _lib.last_error()

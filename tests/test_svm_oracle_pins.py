@@ -32,7 +32,7 @@ def test_decision_matches_exact_rational_arithmetic():
     rng = np.random.default_rng(3)
     P, B, M = 5, 7, 3
     x = rng.uniform(0, 1, (P, B)).astype(np.float32)
-    w = rng.normal(0, 1, (M, B)).astype(np.float32)
+    w = rng.normal(0, 1, (M, B))
     bias = rng.normal(0, 1, M)
     f = so.decision(x, w, bias)
     for p in range(P):
