@@ -19,12 +19,13 @@
 // else is per-pixel arithmetic, so the kernel is HBM-bound.  A block owns 256
 // consecutive pixels.  It stages the cube through LDS in chunks of 32 bands:
 // eight lanes cover one pixel's 128-byte piece of the chunk with 16-byte
-// loads, so every cache line that a load touches is used whole.  Then each
-// lane owns one pixel for the dot products (hyperplane weights at
-// wave-uniform addresses, i.e. scalar loads) and for the coupling iteration,
-// whose sweep count differs from pixel to pixel.  The loads of the next
-// chunk are in flight while the current one is used, so every wave keeps
-// HBM requests outstanding through its dot products.
+// loads, so every cache line that a load touches is used whole.  The
+// hyperplane weights of the chunk (M x 32 values) are staged beside it.
+// Then each lane owns one pixel for the dot products (the weights read as
+// LDS broadcasts: read straight from memory at wave-uniform addresses they
+// became scalar loads whose waits lay on every wave's critical path) and for
+// the coupling iteration, whose sweep count differs from pixel to pixel.
+// The loads of the next chunk are in flight while the current one is used.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -55,6 +56,9 @@ svm_prob_kernel(const float* __restrict__ cube, int64_t npix, int bands,
                 float* __restrict__ out) {
     constexpr int M = C * (C - 1) / 2;
     __shared__ __attribute__((aligned(16))) float tile[SVM_THREADS * SVM_STRIDE];
+    constexpr int NWT = M * SVM_CHUNK;                        // weights of one chunk
+    constexpr int NW = (NWT + SVM_THREADS - 1) / SVM_THREADS;  // per thread
+    __shared__ __attribute__((aligned(16))) double wl[NWT];
     const int tid = threadIdx.x;
     const int64_t first = (int64_t)blockIdx.x * SVM_THREADS;
     const int64_t last = npix - 1;
@@ -72,6 +76,7 @@ svm_prob_kernel(const float* __restrict__ cube, int64_t npix, int bands,
     constexpr int NLOAD = VEC ? 8 : 32;
     using Piece = typename std::conditional<VEC, float4, float>::type;
     Piece v[NLOAD];
+    double wv[NW];
     const int q = VEC ? (tid & 7) : (tid & 31);
     const int r0 = VEC ? (tid >> 3) : (tid >> 5);
     constexpr int RSTEP = VEC ? 32 : 8;
@@ -87,6 +92,12 @@ svm_prob_kernel(const float* __restrict__ cube, int64_t npix, int bands,
             else
                 v[i] = b < bands ? cube[p * (int64_t)bands + b] : 0.f;
         }
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+            const int e = tid + SVM_THREADS * i;   // (m, k) = (e / 32, e % 32)
+            const int bb = c0 + (e % SVM_CHUNK);
+            wv[i] = (e < NWT && bb < bands) ? w[(int64_t)(e / SVM_CHUNK) * bands + bb] : 0.0;
+        }
     };
     fetch(0);
     for (int c0 = 0; c0 < bands; c0 += SVM_CHUNK) {
@@ -97,9 +108,13 @@ svm_prob_kernel(const float* __restrict__ cube, int64_t npix, int bands,
             else
                 tile[(r0 + RSTEP * i) * SVM_STRIDE + q] = v[i];
         }
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+            const int e = tid + SVM_THREADS * i;
+            if (e < NWT) wl[e] = wv[i];
+        }
         __syncthreads();
         if (c0 + SVM_CHUNK < bands) fetch(c0 + SVM_CHUNK);
-        const double* wc = w + c0;
         if (c0 + SVM_CHUNK <= bands) {
 #pragma unroll
             for (int k = 0; k < SVM_CHUNK / 4; ++k) {
@@ -109,14 +124,14 @@ svm_prob_kernel(const float* __restrict__ cube, int64_t npix, int bands,
                 for (int e = 0; e < 4; ++e)
 #pragma unroll
                     for (int m = 0; m < M; ++m)
-                        f[m] = fma(wc[(int64_t)m * bands + 4 * k + e], x[e], f[m]);
+                        f[m] = fma(wl[m * SVM_CHUNK + 4 * k + e], x[e], f[m]);
             }
         } else {
             const int nb = bands - c0;
             for (int k = 0; k < nb; ++k) {
                 const double x = (double)row[k];
 #pragma unroll
-                for (int m = 0; m < M; ++m) f[m] = fma(wc[(int64_t)m * bands + k], x, f[m]);
+                for (int m = 0; m < M; ++m) f[m] = fma(wl[m * SVM_CHUNK + k], x, f[m]);
             }
         }
         __syncthreads();
