@@ -7,7 +7,8 @@ so values agree to a few binary64 ulps before the final rounding: every
 output within 1e-6 of the oracle's (in practice equal or one binary32 ulp
 apart).  Cases cover the 16-byte and the scalar staging paths, band counts
 that leave a partial 32-band chunk, pixel counts that leave a partial block,
-two to eight classes, and the full W 480 x H 380 x 128 cube at every pixel.
+two to eight classes, and the full W 480 x H 380 x 128 and 1000 x 1000 x 100
+cubes at every pixel.
 """
 import sys
 
@@ -70,6 +71,8 @@ CASES = [
     ("C2", 33, 33, 128, 2, "derma"),
     ("C3", 21, 50, 64, 3, "brain"),
     ("C5", 20, 20, 128, 5, "brain"),
+    ("C6", 17, 31, 100, 6, "derma"),
+    ("C7", 23, 29, 40, 7, "brain"),
     ("C8", 19, 23, 96, 8, "brain"),
     ("one-pixel", 1, 1, 128, 4, "brain"),
     ("ragged-block", 1, 257, 128, 4, "brain"),
@@ -111,6 +114,16 @@ def test_svm_full_size_brain_cube(ctx):
     say("svm full-size brain cube")
     got = run_svm(ctx, cube, model, 4)
     check(got, svm_oracle.svm_prob(cube, *model, 4), "full-size")
+
+
+def test_svm_full_size_derma_cube(ctx):
+    """1000 x 1000, 100 bands (400-byte pixel rows: staging pieces straddle
+    cache lines), four classes: every pixel."""
+    cube, _, _ = inputs.g_cube(1000, 1000, 100, 3, "derma")
+    model = inputs.g_svm_model(4, 100, 4)
+    say("svm full-size derma cube")
+    got = run_svm(ctx, cube, model, 4)
+    check(got, svm_oracle.svm_prob(cube, *model, 4), "derma full-size")
 
 
 def test_cube_to_class_map_on_the_device(ctx):
