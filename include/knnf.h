@@ -347,6 +347,8 @@ knnf_status knnf_pc1(knnf_ctx* ctx, const float* cube, int64_t npix, int32_t ban
  * bias, A, B  device, M float64 each (offsets and sigmoid parameters)
  * out      device, npix x classes float32, class fastest; may be the prob
  *          buffer of a knnf_frame
+ * A non-finite cube or model value gives unspecified probabilities for the
+ * pixels it reaches (the kernel still ends normally).
  * Asynchronous on `stream`; no workspace, no allocation.
  * Errors: KNNF_EINVAL for a NULL argument, npix outside [1, 2^31], bands
  * outside [1, KNNF_SVM_MAX_BANDS], classes outside [2, KNNF_SVM_MAX_CLASSES];
