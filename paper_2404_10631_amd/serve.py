@@ -95,9 +95,11 @@ class Server:
         self.close()
 
 
-def replay(server: Server, frames, arrivals, warmup: int = 0, keep=None, timeout_s: float = 120.0):
+def replay(server: Server, frames, arrivals, warmup: int = 0, keep=None, timeout_s: float = 120.0,
+           with_nbr: bool = False):
     """Submit frames[k] at server-clock time t0 + arrivals[k]; release each frame
-    as soon as it is done (after `keep(k, view)` if given).
+    as soon as it is done (after `keep(k, view)` if given).  With `with_nbr`
+    the server also keeps each frame's neighbour indices and distances.
 
     Returns a dict with per-frame latencies (seconds), the server's per-frame
     timestamps (arrival, admission, first launch, completion) and the makespan.
@@ -115,7 +117,7 @@ def replay(server: Server, frames, arrivals, warmup: int = 0, keep=None, timeout
         now = _lib.knnf_server_clock()
         while k < n and t0 + arrivals[order[k]] <= now:
             idx = int(order[k])
-            st, tk = _lib.knnf_server_submit(h, frames[idx].as_c(t0 + arrivals[idx]))
+            st, tk = _lib.knnf_server_submit(h, frames[idx].as_c(t0 + arrivals[idx], with_nbr))
             if st == _lib.KNNF_EAGAIN:
                 break
             tickets[tk] = idx

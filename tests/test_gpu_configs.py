@@ -1,9 +1,9 @@
 """GPU parity at the benchmark's full sizes, in the launch configurations the
 benchmark times: the 64 uneven brain-like frames and the 1024 dermatology-like
 50 x 50 frames in one batched launch, and the mixed S/M/L serving stream
-through the batching server.  Pixels are checked against the oracle at
-sampled positions (the oracle computes them one by one), plus every pixel of
-64 whole small frames; neighbour indices, distances and classes bit-exact,
+through the batching server.  The 1024 small frames are checked at every
+pixel; the uneven and served frames at sampled positions (the oracle computes
+them one by one); neighbour indices, distances and classes bit-exact,
 probabilities within 1e-6.
 """
 import sys
@@ -86,7 +86,7 @@ def test_config2_uneven_batch_full_size(ctx, plan):
 def test_config3_small_frame_batch_full_size(ctx):
     """1024 derma-like 50 x 50 frames, K = 16, +-7 rows, one batched launch
     (the default grid launch; the persistent launch must give the same bits):
-    64 whole frames at every pixel, 24 sampled pixels of every other frame."""
+    every frame at every pixel against the oracle."""
     import torch
 
     wl = inputs.config3()
@@ -102,27 +102,22 @@ def test_config3_small_frame_batch_full_size(ctx):
     say("config3: one batched launch, default plan")
     _lib.knnf_filter_batch(ctx, [f.as_c() for f in frames], None, current_stream())
     torch.cuda.synchronize()
-    rng = np.random.default_rng(8)
-    whole = set(range(0, 1024, 16))
     for k, (s, d, f) in enumerate(zip(wl.frames, data, frames)):
         go, gc, gn, gd = f.results()
         for x, y in zip((go, gc, gn, gd), persistent[k]):
             assert np.array_equal(x, y), f"config3 frame {k}: launch modes differ"
-        if k in whole:
-            ro, rc, rn, rd = oracle.knn_filter(d[0], d[1], s.K, s.R, s.lam)
-            assert np.array_equal(gn, rn) and np.array_equal(gc, rc), f"config3 frame {k}"
-            assert np.array_equal(gd.view(np.uint32), rd.view(np.uint32)), f"config3 frame {k}"
-            assert float(np.max(np.abs(go.astype(np.float64) - ro))) <= PROB_TOL
-        else:
-            check_sampled(f"config3 frame {k}", s, d, (go, gc, gn, gd),
-                          sample_pixels(s.H, s.W, 24, rng))
-    say("config3: 64 whole frames and sampled pixels bit-exact")
+        ro, rc, rn, rd = oracle.knn_filter(d[0], d[1], s.K, s.R, s.lam)
+        assert np.array_equal(gn, rn) and np.array_equal(gc, rc), f"config3 frame {k}"
+        assert np.array_equal(gd.view(np.uint32), rd.view(np.uint32)), f"config3 frame {k}"
+        assert float(np.max(np.abs(go.astype(np.float64) - ro))) <= PROB_TOL
+    say("config3: all 1024 frames bit-exact at every pixel")
 
 
 def test_config4_served_mix_full_size(ctx):
     """The serving stream's S/M/L classes at full size (50x50 K=16 +-7,
     W480xH380 K=40 +-14, 1000x1000 K=40 +-14), Poisson arrivals, through the
-    batching server; every frame checked at sampled pixels."""
+    batching server, neighbour outputs kept; every frame checked at sampled
+    pixels (indices, distances, classes, probabilities)."""
     stream = inputs.serve_stream(n=40, rate_hz=2000.0, seed=11)
     specs = [s for _, _, s in stream]
     arrivals = [t for t, _, _ in stream]
@@ -134,10 +129,12 @@ def test_config4_served_mix_full_size(ctx):
     results = {}
     say("config4: replaying through the server")
     with Server(ctx, pool) as srv:
-        replay(srv, hosts, arrivals, keep=lambda k, v: results.__setitem__(k, srv.view_arrays(v)))
+        replay(srv, hosts, arrivals, keep=lambda k, v: results.__setitem__(k, srv.view_arrays(v)),
+               with_nbr=True)
     rng = np.random.default_rng(9)
     for k, (s, d) in enumerate(zip(specs, data)):
-        go, gc, _, _ = results[k]
-        check_sampled(f"config4 frame {k} ({s.H}x{s.W})", s, d, (go, gc, None, None),
+        go, gc, gn, gd = results[k]
+        assert gn is not None and gd is not None
+        check_sampled(f"config4 frame {k} ({s.H}x{s.W})", s, d, (go, gc, gn, gd),
                       sample_pixels(s.H, s.W, 64, rng))
     say("config4: sampled pixels bit-exact")
