@@ -40,13 +40,21 @@
  * and outputs untouched until the stream has reached the call.  Parameter
  * validation is synchronous and happens before anything is enqueued.
  *
- * Errors: functions return a knnf_status.  KNNF_EINVAL leaves the context
- * usable.  A HIP launch failure returns KNNF_EDEVICE.  knnf_last_error() gives
- * a text description of the last failure on the calling thread.
- *
- * Inputs are expected to be finite.  Non-finite values do not make the library
- * read or write out of bounds, but the selected neighbours are then
- * unspecified.
+ * Errors: functions return a knnf_status.  Validation is synchronous and
+ * happens before anything is enqueued; KNNF_EINVAL leaves the context usable.
+ * It covers sizes, parameters, pointers and, unless the plan's
+ * KNNF_PLAN_NO_INPUT_CHECK flag is set, the input values: a non-finite pc1 or
+ * prob value (NaN or +-inf) is rejected with KNNF_EINVAL.  That check is one
+ * device pass over the inputs on the caller's stream, after which the call
+ * waits for the stream (so the check makes the call synchronous); nothing else
+ * is enqueued when it fails.  With the check skipped the caller vouches for
+ * finite inputs: non-finite values then do not make the library read or write
+ * out of bounds, but the selected neighbours are unspecified.
+ * A failed HIP call returns KNNF_EDEVICE and marks the context as failed: every
+ * later call on it (and on servers created on it) returns KNNF_EDEVICE
+ * ("sticky"), since device state after a failure cannot be trusted; destroy the
+ * context.  knnf_last_error() gives a text description of the last failure on
+ * the calling thread.
  */
 #ifndef KNNF_H
 #define KNNF_H
@@ -116,16 +124,27 @@ typedef enum { KNNF_SEARCH_EXHAUSTIVE = 0, KNNF_SEARCH_PRUNED = 1 } knnf_search;
  *   tile_cols     supported tiles (rows x cols): 1x8, 1x16, 2x4, 2x8, 4x4
  *   waves         wavefronts per workgroup; 1, 2 or 4
  *   launch        knnf_launch (batched launches only)
- * A zero tile, wave or launch field means "the context's default" (initially a pruned
- * search with 1 x 8 tiles, one wavefront per workgroup and grid launches);
- * search is always taken from the plan (0 = exhaustive).
+ *   chunk_rows    window chunk of the pruned search: the candidates a
+ *                 wavefront evaluates per step form a patch of chunk_rows rows
+ *                 x (64 / chunk_rows) columns; 8, 16 or 32 (the exhaustive
+ *                 search always sweeps 4 rows x 64 columns)
+ *   flags         KNNF_PLAN_* bits
+ * A zero tile, wave, launch or chunk field means "the context's default"
+ * (initially a pruned search with 1 x 8 tiles, one wavefront per workgroup,
+ * grid launches and 16-row chunks); search and flags are always taken from
+ * the plan (0 = exhaustive, input check on).  Every plan gives bitwise
+ * identical outputs.
  */
+#define KNNF_PLAN_NO_INPUT_CHECK 1 /* skip the non-finite input check */
+
 typedef struct {
     int32_t search;
     int32_t tile_rows;
     int32_t tile_cols;
     int32_t waves;
-    int32_t launch;  /* batched launches: knnf_launch                            */
+    int32_t launch;     /* batched launches: knnf_launch                          */
+    int32_t chunk_rows; /* pruned search: window chunk rows (8, 16, 32)           */
+    int32_t flags;      /* KNNF_PLAN_* bits                                       */
 } knnf_plan;
 
 /*
@@ -139,11 +158,29 @@ typedef struct {
  */
 typedef enum { KNNF_LAUNCH_DEFAULT = 0, KNNF_LAUNCH_PERSISTENT = 1, KNNF_LAUNCH_GRID = 2 } knnf_launch;
 
-/* Create a context on HIP device `device` (ordinal).  *out is NULL on error. */
+/*
+ * Create a context on HIP device `device` (ordinal).  *out is NULL on error
+ * (KNNF_EDEVICE when no HIP device is usable).  If the environment variable
+ * KNNF_TUNE_CACHE names a readable file written by knnf_tune, its plans are
+ * loaded (see knnf_tune).
+ */
 knnf_status knnf_create(knnf_ctx** out, int device);
 
 /* Free the context and its device workspace.  NULL is accepted. */
 knnf_status knnf_destroy(knnf_ctx* ctx);
+
+/*
+ * KNNF_OK, or KNNF_EDEVICE once a HIP call on the context has failed (the
+ * context stays failed).  KNNF_EINVAL for NULL.
+ */
+knnf_status knnf_ctx_status(const knnf_ctx* ctx);
+
+/*
+ * Marks the context as failed exactly as a failed HIP call would (every later
+ * call returns KNNF_EDEVICE).  For testing how callers handle device failures;
+ * launches nothing.
+ */
+knnf_status knnf_inject_fault(knnf_ctx* ctx);
 
 /* Default plan used when a call passes no plan (NULL).  Validated. */
 knnf_status knnf_set_default_plan(knnf_ctx* ctx, const knnf_plan* plan);
@@ -157,7 +194,9 @@ knnf_status knnf_validate(const knnf_frame* frame);
 
 /*
  * Filter one frame (Sec. II.C.3, Eq. 1 and 2) with one kernel launch on
- * `stream`.  plan may be NULL.
+ * `stream` (two with the input check).  plan may be NULL: then the plan
+ * knnf_tune cached for the frame's (H, W, K, R, C), else the context's
+ * default.
  */
 knnf_status knnf_filter(knnf_ctx* ctx, const knnf_frame* frame,
                         const knnf_plan* plan, void* stream);
@@ -169,20 +208,36 @@ knnf_status knnf_filter(knnf_ctx* ctx, const knnf_frame* frame,
  * wavefronts claim tasks from a shared counter).  Every frame's outputs are bitwise
  * equal to knnf_filter() of that frame alone.  The frame table is copied to
  * the context's device workspace with an asynchronous copy on `stream`; the
- * caller's array may be reused when the call returns.  Calls on one context
- * must not run concurrently from several host threads.
+ * caller's array may be reused when the call returns.  plan may be NULL: then
+ * the plan knnf_tune cached for this frame list, else the context's default.
+ * Calls on one context must not run concurrently from several host threads.
  */
 knnf_status knnf_filter_batch(knnf_ctx* ctx, const knnf_frame* frames, int n,
                               const knnf_plan* plan, void* stream);
 
 /*
- * Autotuner: time each candidate plan on the given frames (device buffers of
- * the caller; their outputs are overwritten) and keep the fastest per shape
- * bucket.  `reps` timed repetitions per plan (>= 1).  Synchronises the stream.
- * The chosen plan for the frame set is written to *best when best != NULL.
+ * Autotuner: times every plan -- search, tile shape, waves, window chunk
+ * (pruned search) and, for n > 1, launch mode -- on the given frames (device
+ * buffers of the caller; their outputs are overwritten), `reps` timed
+ * repetitions each (>= 1) after one warm-up, with HIP events on `stream`
+ * (synchronised).  The fastest plan is written to *best (if not NULL) and
+ * cached in the context under the frames' key: for n = 1 the frame's
+ * (H, W, K, R, C); for n > 1 the list of those tuples in order.  Calls that
+ * pass no plan use the cached plan of their key.  If KNNF_TUNE_CACHE was set
+ * when the context was created, the cache is also written to that file as
+ * JSON after every tuning (and read back by later contexts); KNNF_EINVAL if
+ * it cannot be written (the plan is still cached in the context and in *best).
  */
 knnf_status knnf_tune(knnf_ctx* ctx, const knnf_frame* frames, int n, int reps,
                       void* stream, knnf_plan* best);
+
+/*
+ * The plan a call without a plan would use for these frames: the cached plan
+ * of their key (returns KNNF_OK) or the context's default (returns
+ * KNNF_ESTATE: nothing cached).  Frames are validated (sizes only).
+ */
+knnf_status knnf_tune_lookup(const knnf_ctx* ctx, const knnf_frame* frames, int n,
+                             knnf_plan* plan);
 
 /*
  * Work counters of the filtering kernels, for roofline accounting.  While
@@ -230,7 +285,9 @@ typedef struct {
     int32_t step_tiles;    /* tile budget of one batched step; 0: 32768 (a lone  */
                            /* frame with nothing waiting runs whole)             */
     knnf_plan plan;        /* kernel plan; zero fields: the context's default,    */
-                           /* except launch, which defaults to KNNF_LAUNCH_GRID   */
+                           /* except launch, which defaults to KNNF_LAUNCH_GRID;  */
+                           /* without KNNF_PLAN_NO_INPUT_CHECK, submit checks     */
+                           /* the host inputs for non-finite values               */
 } knnf_server_opts;
 
 typedef struct {
@@ -266,9 +323,11 @@ knnf_status knnf_server_create(knnf_server** out, knnf_ctx* ctx, void* pool,
                                size_t pool_bytes, const knnf_server_opts* opts);
 
 /*
- * Submit a frame.  Returns a ticket.  KNNF_EINVAL for a bad frame,
- * KNNF_ENOMEM if the frame can never fit the pool, KNNF_EAGAIN if the
- * admission queue is full (retry later).
+ * Submit a frame.  Returns a ticket.  KNNF_EINVAL for a bad frame (including
+ * non-finite input values, checked on the host unless the server's plan has
+ * KNNF_PLAN_NO_INPUT_CHECK), KNNF_ENOMEM if the frame can never fit the pool,
+ * KNNF_EAGAIN if the admission queue is full (retry later), KNNF_EDEVICE once
+ * the server or its context has failed.
  */
 knnf_status knnf_server_submit(knnf_server* srv, const knnf_host_frame* frame,
                                uint64_t* ticket);

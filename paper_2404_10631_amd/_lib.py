@@ -49,14 +49,19 @@ KNNF_LAUNCH_PERSISTENT = 1
 KNNF_LAUNCH_GRID = 2
 
 
+KNNF_PLAN_NO_INPUT_CHECK = 1
+
+
 class knnf_plan(ctypes.Structure):
     _fields_ = [("search", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("tile_cols", ctypes.c_int32), ("waves", ctypes.c_int32),
-                ("launch", ctypes.c_int32)]
+                ("launch", ctypes.c_int32), ("chunk_rows", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
 
     def as_dict(self):
         return {"search": self.search, "tile_rows": self.tile_rows,
-                "tile_cols": self.tile_cols, "waves": self.waves, "launch": self.launch}
+                "tile_cols": self.tile_cols, "waves": self.waves, "launch": self.launch,
+                "chunk_rows": self.chunk_rows, "flags": self.flags}
 
 
 def make_plan(plan) -> "knnf_plan":
@@ -64,7 +69,8 @@ def make_plan(plan) -> "knnf_plan":
         return plan
     return knnf_plan(int(plan.get("search", 0)), int(plan.get("tile_rows", 0)),
                      int(plan.get("tile_cols", 0)), int(plan.get("waves", 0)),
-                     int(plan.get("launch", 0)))
+                     int(plan.get("launch", 0)), int(plan.get("chunk_rows", 0)),
+                     int(plan.get("flags", 0)))
 
 
 KNNF_SERVE_BATCHED = 0
@@ -104,6 +110,9 @@ _I = ctypes.c_int
 _SIGS = {
     "knnf_create": (_I, [ctypes.POINTER(_P), _I]),
     "knnf_destroy": (_I, [_P]),
+    "knnf_ctx_status": (_I, [_P]),
+    "knnf_inject_fault": (_I, [_P]),
+    "knnf_tune_lookup": (_I, [_P, ctypes.POINTER(knnf_frame), _I, ctypes.POINTER(knnf_plan)]),
     "knnf_set_default_plan": (_I, [_P, ctypes.POINTER(knnf_plan)]),
     "knnf_get_default_plan": (_I, [_P, ctypes.POINTER(knnf_plan)]),
     "knnf_validate": (_I, [ctypes.POINTER(knnf_frame)]),
@@ -182,6 +191,26 @@ def knnf_create(device: int = 0) -> int:
 
 def knnf_destroy(ctx: int) -> None:
     check(load().knnf_destroy(ctx))
+
+
+def knnf_ctx_status(ctx: int) -> int:
+    """KNNF_OK, or KNNF_EDEVICE once the context has failed (returned, not raised)."""
+    return int(load().knnf_ctx_status(ctx))
+
+
+def knnf_inject_fault(ctx: int) -> None:
+    check(load().knnf_inject_fault(ctx))
+
+
+def knnf_tune_lookup(ctx: int, frames) -> tuple[int, knnf_plan]:
+    """(status, plan): KNNF_OK and the cached plan, or KNNF_ESTATE and the
+    context's default plan."""
+    arr, n = _frames_arg(frames)
+    p = knnf_plan()
+    st = load().knnf_tune_lookup(ctx, arr, n, ctypes.byref(p))
+    if st not in (KNNF_OK, KNNF_ESTATE):
+        check(st)
+    return int(st), p
 
 
 def knnf_set_default_plan(ctx: int, plan) -> None:

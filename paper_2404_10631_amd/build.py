@@ -44,8 +44,10 @@ DEVICE_FLAGS = [
 
 
 def build(verbose: bool = False, extra: list[str] | None = None) -> str:
-    """Compile every source into ``libknnf.so``; returns its path."""
-    objs = []
+    """Compile every source into ``libknnf.so`` (sources in parallel); returns its path."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    cmds, objs = [], []
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(CSRC, src + ".o")
@@ -55,8 +57,11 @@ def build(verbose: bool = False, extra: list[str] | None = None) -> str:
         cmd += ["-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        cmds.append(cmd)
         objs.append(obj)
+    with ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 1)) as ex:
+        for r in list(ex.map(lambda c: subprocess.run(c, check=True), cmds)):
+            pass
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:

@@ -27,6 +27,7 @@ struct LaunchCfg {
     int waves;     // wavefronts per workgroup: 1, 2, 4
     int pruned;    // 0 exhaustive, 1 pruned
     int persistent;  // batched launches: 1 persistent claim loop, 0 one wavefront per task
+    int chunk_log2;  // pruned search: log2 of the patch rows (3, 4, 5)
 };
 
 // Host-side launchers (defined in knnf_kernels.hip).  Return hipError_t as int.
@@ -36,6 +37,13 @@ int launch_filter_batch(const FrameDesc* d_frames, const uint32_t* d_task_start,
                         uint32_t* d_counter, const LaunchCfg& cfg, int grid_blocks, void* stream);
 // Zero the batched kernel's claim counter.
 int launch_zero_counter(uint32_t* d_counter, void* stream);
+
+// Non-finite input check: the kernels store `gen` to *flag (device-visible
+// host memory) when any pc1 or prob value of the frames is not finite.
+// max_words: the largest H*W*(C+1) of the table's frames (sizes the grid).
+int launch_check_frame(const FrameDesc& f, uint32_t* flag, uint32_t gen, void* stream);
+int launch_check_items(const FrameDesc* d_frames, uint32_t n, uint32_t max_words, uint32_t* flag,
+                       uint32_t gen, void* stream);
 
 // A batch table small enough to travel as a kernel argument: run k copies
 // len[k] words from w[src[k]] to d_base[dst[k]].  Writing a small table this

@@ -31,4 +31,10 @@ knnf_status launch_items(knnf_ctx* ctx, const WorkItem* items, int n, const knnf
 // Device ordinal of a context.
 int ctx_device(const knnf_ctx* ctx);
 
+// KNNF_EDEVICE (and the message) once the context has failed, else KNNF_OK.
+knnf_status ctx_status(const knnf_ctx* ctx);
+
+// Mark the context failed (a server's HIP call failed on it).
+void ctx_mark_failed(knnf_ctx* ctx, const char* what);
+
 }  // namespace knnf

@@ -337,9 +337,10 @@ __device__ __forceinline__ uint64_t flush_query(TileState<QR, QC>& S, const Fram
 // >= 0 and binary32 rounding is monotone, so fmaf(b, b, a2) with the smallest
 // |b| and a2 of a set of candidates bounds all their distances from below;
 // a set whose bound exceeds every query's current bound tau cannot hold a
-// neighbour.  The scan visits the window in patches of 16 rows x 4 columns:
-// lane L holds row blk + (L & 15), column jc + (L >> 4), so a lane's row term
-// stays fixed while a row block is swept outward column step by column step.
+// neighbour.  The scan visits the window in patches of PR rows x 64/PR
+// columns (the window chunk, PR = 2^lpr = 8, 16 or 32): lane L holds row
+// blk + (L % PR), column jc + L / PR, so a lane's row term stays fixed while a
+// row block is swept outward column step by column step.
 //   * live rows: rows where some query's row term alone is within its bound
 //     (its own column has b = 0);
 //   * per block of 16 live rows: the tile's own column steps, then steps to
@@ -350,7 +351,7 @@ __device__ __forceinline__ uint64_t flush_query(TileState<QR, QC>& S, const Fram
 // tightens its bound.
 template <int QR, int QC>
 __device__ __forceinline__ void scan_pruned(TileState<QR, QC>& S, const FrameDesc& f, int r0,
-                                            int c0, int nqr, int nqc,
+                                            int c0, int nqr, int nqc, int lpr,
                                             const float (&iq)[QR * QC],
                                             uint32_t (&th)[QR * QC], int (&cnt)[QR * QC],
                                             unsigned long long& pairs) {
@@ -391,10 +392,11 @@ __device__ __forceinline__ void scan_pruned(TileState<QR, QC>& S, const FrameDes
         }
     }
 
-    const int lr = L & 15, lc = L >> 4;
-    const int ncen = (nqc + 3) >> 2;  // steps over the tile's own columns
-    for (int blk = lo; blk <= hi; blk += 16) {
-        const int bhi = min(blk + 15, hi);
+    const int PR = 1 << lpr, lsw = 6 - lpr, SW = 1 << lsw;  // patch rows, step columns
+    const int lr = L & (PR - 1), lc = L >> lpr;
+    const int ncen = (nqc + SW - 1) >> lsw;  // steps over the tile's own columns
+    for (int blk = lo; blk <= hi; blk += PR) {
+        const int bhi = min(blk + PR - 1, hi);
         const int i = blk + lr;
         float a2[QR];   // this lane's row term per query row
         bool rok[QR];   // this lane's row is live and in the query row's window
@@ -420,8 +422,8 @@ __device__ __forceinline__ void scan_pruned(TileState<QR, QC>& S, const FrameDes
             int n = 0;
             for (;;) {
                 const int st = n + L;
-                const int jc = side == 0 ? c0 + 4 * (ncen + st) : c0 - 4 * (st + 1);
-                const int jn = side == 0 ? jc : jc + 3;  // the step's column nearest the tile
+                const int jc = side == 0 ? c0 + SW * (ncen + st) : c0 - SW * (st + 1);
+                const int jn = side == 0 ? jc : jc + SW - 1;  // the step's column nearest the tile
                 const float fj = feat(lam, jn);
                 uint64_t m = 0;
 #pragma unroll
@@ -441,7 +443,7 @@ __device__ __forceinline__ void scan_pruned(TileState<QR, QC>& S, const FrameDes
         // rows past the frame or the window are loaded clamped and never pass
         const float* __restrict__ rowp = pc1 + (size_t)min(i, rhi) * W;
         auto step_col = [&](int st) {
-            return st < ncen + nright ? c0 + 4 * st : c0 - 4 * (st - ncen - nright + 1);
+            return st < ncen + nright ? c0 + SW * st : c0 - SW * (st - ncen - nright + 1);
         };
         float ipn = rowp[min(max(step_col(0) + lc, 0), W - 1)];
         for (int st = 0; st < ns; ++st) {
@@ -541,7 +543,7 @@ __device__ __forceinline__ float gather_add(float s, const char* __restrict__ pb
 // Process one tile: query pixels (r0 + qr, c0 + qc), qr < QR, qc < QC.
 template <int QR, int QC, bool PRUNE>
 __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const FrameDesc& f, int r0,
-                                             int c0) {
+                                             int c0, int lpr) {
     constexpr int Q = QR * QC;
     const int L = lane_id();
     const int H = f.H, W = f.W, R = f.R, K = f.K, C = f.C;
@@ -649,7 +651,7 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
 
     // ---- pass B
     if constexpr (PRUNE) {
-        scan_pruned<QR, QC>(S, f, r0, c0, nqr, nqc, iq, th, cnt, pairs);
+        scan_pruned<QR, QC>(S, f, r0, c0, nqr, nqc, lpr, iq, th, cnt, pairs);
     } else {
         // exhaustive: window rows x 64-column chunks, nearest chunk first
         const int rlo = max(0, r0 - R);
@@ -957,7 +959,7 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 
 template <int QR, int QC, int WPB, bool PRUNE>
 __global__ void __launch_bounds__(WPB * WAVE) KNNF_WAVES_PER_EU(QR, QC)
-filter_frame_kernel(FrameDesc f) {
+filter_frame_kernel(FrameDesc f, int lpr) {
     __shared__ TileLds<QR, QC, PRUNE> lds[WPB];
     const int w = uni((int)(threadIdx.x >> 6));
     const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
@@ -968,7 +970,7 @@ filter_frame_kernel(FrameDesc f) {
     if (s >= ntiles) return;
     const uint32_t band = s / ntc;
     const uint32_t tc = s - band * ntc;
-    process_tile<QR, QC, PRUNE>(lds[w], f, (int)band * QR, (int)tc * QC);
+    process_tile<QR, QC, PRUNE>(lds[w], f, (int)band * QR, (int)tc * QC, lpr);
 }
 
 // Persistent batched kernel: each wavefront claims tile tasks from one global
@@ -984,7 +986,7 @@ template <int QR, int QC, int WPB, bool PRUNE>
 __global__ void __launch_bounds__(WPB * WAVE) KNNF_WAVES_PER_EU(QR, QC)
 filter_batch_kernel(const FrameDesc* __restrict__ frames, const uint32_t* __restrict__ task_start,
                     const uint32_t* __restrict__ tile_base, uint32_t nframes, uint32_t total_tasks,
-                    uint32_t claim, uint32_t* counter) {
+                    uint32_t claim, uint32_t* counter, int lpr) {
     __shared__ TileLds<QR, QC, PRUNE> lds[WPB];
     const int w = uni((int)(threadIdx.x >> 6));
     const int L = lane_id();
@@ -1012,7 +1014,7 @@ filter_batch_kernel(const FrameDesc* __restrict__ frames, const uint32_t* __rest
             const uint32_t ntc = (uint32_t)((f.W + QC - 1) / QC);
             const int band = (int)(s / ntc);
             const int tc = (int)(s - (uint32_t)band * ntc);
-            process_tile<QR, QC, PRUNE>(lds[w], f, band * QR, tc * QC);
+            process_tile<QR, QC, PRUNE>(lds[w], f, band * QR, tc * QC, lpr);
         }
     }
 }
@@ -1023,7 +1025,7 @@ template <int QR, int QC, int WPB, bool PRUNE>
 __global__ void __launch_bounds__(WPB * WAVE) KNNF_WAVES_PER_EU(QR, QC)
 filter_items_kernel(const FrameDesc* __restrict__ frames, const uint32_t* __restrict__ task_start,
                     const uint32_t* __restrict__ tile_base, uint32_t nframes,
-                    uint32_t total_tasks) {
+                    uint32_t total_tasks, int lpr) {
     __shared__ TileLds<QR, QC, PRUNE> lds[WPB];
     const int w = uni((int)(threadIdx.x >> 6));
     const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
@@ -1040,35 +1042,35 @@ filter_items_kernel(const FrameDesc* __restrict__ frames, const uint32_t* __rest
     const uint32_t ntc = (uint32_t)((f.W + QC - 1) / QC);
     const int band = (int)(s / ntc);
     const int tc = (int)(s - (uint32_t)band * ntc);
-    process_tile<QR, QC, PRUNE>(lds[w], f, band * QR, tc * QC);
+    process_tile<QR, QC, PRUNE>(lds[w], f, band * QR, tc * QC, lpr);
 }
 
 template <int QR, int QC, int WPB, bool PRUNE>
 int launch_items_t(const FrameDesc* fr, const uint32_t* ts, const uint32_t* tb, uint32_t n,
-                   uint32_t tot, hipStream_t st) {
+                   uint32_t tot, int lpr, hipStream_t st) {
     const uint64_t blocks = ((uint64_t)tot + WPB - 1) / WPB;
     hipLaunchKernelGGL((filter_items_kernel<QR, QC, WPB, PRUNE>), dim3((unsigned)blocks),
-                       dim3(WPB * WAVE), 0, st, fr, ts, tb, n, tot);
+                       dim3(WPB * WAVE), 0, st, fr, ts, tb, n, tot, lpr);
     return (int)hipGetLastError();
 }
 
 template <int QR, int QC, int WPB, bool PRUNE>
-int launch_frame_t(const FrameDesc& f, hipStream_t st) {
+int launch_frame_t(const FrameDesc& f, int lpr, hipStream_t st) {
     const long long tiles = (long long)((f.H + QR - 1) / QR) * ((f.W + QC - 1) / QC);
     const long long blocks = (tiles + WPB - 1) / WPB;
     hipLaunchKernelGGL((filter_frame_kernel<QR, QC, WPB, PRUNE>), dim3((unsigned)blocks),
-                       dim3(WPB * WAVE), 0, st, f);
+                       dim3(WPB * WAVE), 0, st, f, lpr);
     return (int)hipGetLastError();
 }
 
 template <int QR, int QC, int WPB, bool PRUNE>
 int launch_batch_t(const FrameDesc* fr, const uint32_t* ts, const uint32_t* tb, uint32_t n,
-                   uint32_t tot, uint32_t* ctr, int grid, hipStream_t st) {
+                   uint32_t tot, uint32_t* ctr, int grid, int lpr, hipStream_t st) {
     // at least four claims per resident wavefront, at most 8 tasks per claim
     const uint64_t waves = (uint64_t)grid * WPB;
     const uint32_t claim = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(8, tot / (waves * 4)));
     hipLaunchKernelGGL((filter_batch_kernel<QR, QC, WPB, PRUNE>), dim3((unsigned)grid),
-                       dim3(WPB * WAVE), 0, st, fr, ts, tb, n, tot, claim, ctr);
+                       dim3(WPB * WAVE), 0, st, fr, ts, tb, n, tot, claim, ctr, lpr);
     return (int)hipGetLastError();
 }
 
@@ -1108,7 +1110,7 @@ int occupancy_t() {
 
 int launch_filter_frame(const FrameDesc& f, const LaunchCfg& cfg, void* stream) {
     hipStream_t st = (hipStream_t)stream;
-    KNNF_DISPATCH(launch_frame_t, f, st);
+    KNNF_DISPATCH(launch_frame_t, f, cfg.chunk_log2, st);
 }
 
 int launch_filter_batch(const FrameDesc* d_frames, const uint32_t* d_task_start,
@@ -1116,7 +1118,7 @@ int launch_filter_batch(const FrameDesc* d_frames, const uint32_t* d_task_start,
                         uint32_t* d_counter, const LaunchCfg& cfg, int grid_blocks, void* stream) {
     hipStream_t st = (hipStream_t)stream;
     KNNF_DISPATCH(launch_batch_t, d_frames, d_task_start, d_tile_base, nframes, total_tasks,
-                  d_counter, grid_blocks, st);
+                  d_counter, grid_blocks, cfg.chunk_log2, st);
 }
 
 int persistent_blocks_per_cu(const LaunchCfg& cfg) { KNNF_DISPATCH(occupancy_t); }
@@ -1125,7 +1127,72 @@ int launch_filter_items(const FrameDesc* d_frames, const uint32_t* d_task_start,
                         const uint32_t* d_tile_base, uint32_t nframes, uint32_t total_tasks,
                         const LaunchCfg& cfg, void* stream) {
     hipStream_t st = (hipStream_t)stream;
-    KNNF_DISPATCH(launch_items_t, d_frames, d_task_start, d_tile_base, nframes, total_tasks, st);
+    KNNF_DISPATCH(launch_items_t, d_frames, d_task_start, d_tile_base, nframes, total_tasks,
+                  cfg.chunk_log2, st);
+}
+
+// ---- Input check (validation before a launch): *flag = gen when any pc1 or
+// prob value of the frames is NaN or infinite (exponent bits all ones).
+__device__ __forceinline__ bool nonfinite(uint32_t u) { return (u & 0x7f800000u) == 0x7f800000u; }
+
+// Any non-finite value among words t0, t0 + stride, ... of n words at p
+// (16-byte loads where p is 16-byte aligned).
+__device__ __forceinline__ bool scan_nonfinite(const float* p, size_t n, size_t t0, size_t stride) {
+    bool bad = false;
+    size_t k = t0;
+    if (((uintptr_t)p & 15) == 0) {
+        const uint4* __restrict__ q = (const uint4*)p;
+        const size_t n4 = n >> 2;
+        for (; k < n4; k += stride) {
+            const uint4 v = q[k];
+            bad = bad || nonfinite(v.x) || nonfinite(v.y) || nonfinite(v.z) || nonfinite(v.w);
+        }
+        k = (n4 << 2) + t0;
+    }
+    const uint32_t* __restrict__ w = (const uint32_t*)p;
+    for (; k < n; k += stride) bad = bad || nonfinite(w[k]);
+    return bad;
+}
+
+__device__ __forceinline__ void check_frame(const FrameDesc& f, size_t t0, size_t stride,
+                                            uint32_t* flag, uint32_t gen) {
+    const size_t px = (size_t)f.H * (size_t)f.W;
+    const bool bad = scan_nonfinite(f.pc1, px, t0, stride) ||
+                     scan_nonfinite(f.prob, px * (size_t)f.C, t0, stride);
+    if (ballot(bad) && lane_id() == 0)
+        __hip_atomic_store(flag, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__global__ void __launch_bounds__(256) check_frame_kernel(FrameDesc f, uint32_t* flag, uint32_t gen) {
+    check_frame(f, (size_t)blockIdx.x * blockDim.x + threadIdx.x, (size_t)gridDim.x * blockDim.x,
+                flag, gen);
+}
+
+// Frames of a batch table: blockIdx.y strides over the frames, blockIdx.x
+// over each frame's values.
+__global__ void __launch_bounds__(256)
+check_items_kernel(const FrameDesc* __restrict__ frames, uint32_t n, uint32_t* flag, uint32_t gen) {
+    for (uint32_t k = blockIdx.y; k < n; k += gridDim.y)
+        check_frame(frames[k], (size_t)blockIdx.x * blockDim.x + threadIdx.x,
+                    (size_t)gridDim.x * blockDim.x, flag, gen);
+}
+
+int launch_check_frame(const FrameDesc& f, uint32_t* flag, uint32_t gen, void* stream) {
+    const size_t words = (size_t)f.H * (size_t)f.W * (size_t)(f.C + 1);
+    // about 16 words per thread, at most 1024 workgroups
+    const size_t blocks = std::min<size_t>(1024, std::max<size_t>(1, words / (256 * 16)));
+    hipLaunchKernelGGL(check_frame_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                       (hipStream_t)stream, f, flag, gen);
+    return (int)hipGetLastError();
+}
+
+int launch_check_items(const FrameDesc* d_frames, uint32_t n, uint32_t max_words, uint32_t* flag,
+                       uint32_t gen, void* stream) {
+    const unsigned bx = (unsigned)std::min<size_t>(64, std::max<size_t>(1, max_words / (256 * 16)));
+    const unsigned by = std::min<unsigned>(n, 65535u);
+    hipLaunchKernelGGL(check_items_kernel, dim3(bx, by), dim3(256), 0, (hipStream_t)stream,
+                       d_frames, n, flag, gen);
+    return (int)hipGetLastError();
 }
 
 __global__ void zero_counter_kernel(uint32_t* p) { *p = 0u; }

@@ -132,6 +132,7 @@ struct knnf_server {
     std::thread thread;
     std::thread copier;
     knnf_status sticky = KNNF_OK;
+    bool check_inputs = true;   // reject non-finite host inputs at submission
 
     explicit knnf_server(size_t pool_bytes) : alloc(pool_bytes) {}
 };
@@ -169,6 +170,20 @@ hipEvent_t take_event(knnf_server* s) {
     hipEvent_t e = nullptr;
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
     return e;
+}
+
+// A HIP call of the server failed: the server and its context stay failed.
+void server_fail(knnf_server* s, const char* what) {
+    s->sticky = KNNF_EDEVICE;
+    knnf::ctx_mark_failed(s->ctx, what);
+}
+
+// Any NaN or infinity among n binary32 values (exponent bits all ones).
+bool has_nonfinite(const float* v, size_t n) {
+    const uint32_t* w = (const uint32_t*)v;
+    uint32_t bad = 0;
+    for (size_t k = 0; k < n; ++k) bad |= ((w[k] & 0x7f800000u) == 0x7f800000u);
+    return bad != 0;
 }
 
 // Lay out a frame in the pool: inputs, then outputs, 256-byte aligned.
@@ -230,7 +245,7 @@ void admit(knnf_server* s) {
                 enqueue_copies(s, (void*)j.dev.pc1, j.hf.pc1, px * 4, (void*)j.dev.prob, j.hf.prob,
                                px * (size_t)j.hf.C * 4, j.copied);
             if (e != hipSuccess) {
-                s->sticky = KNNF_EDEVICE;
+                server_fail(s, "server: input copy");
                 return;
             }
             j.state = ADMITTED;
@@ -279,7 +294,7 @@ void copier(knnf_server* s) {
         s->copier_busy = false;
         if (e != hipSuccess) {
             // the frame never becomes ready; polls and drain report the error
-            s->sticky = KNNF_EDEVICE;
+            server_fail(s, "server: input copy");
             if (ev) s->event_pool.push_back(ev);
             continue;
         }
@@ -309,7 +324,7 @@ bool reap(knnf_server* s) {
         if (!st.active) continue;
         const hipError_t q = hipEventQuery(st.done);
         if (q == hipErrorNotReady) continue;
-        if (q != hipSuccess) s->sticky = KNNF_EDEVICE;
+        if (q != hipSuccess) server_fail(s, "server: step completion");
         const double t = now_s();
         for (uint64_t tk : st.tickets) {
             Job& j = s->jobs[tk];
@@ -347,7 +362,8 @@ bool launch_step(knnf_server* s) {
         // of them waits for the copy of its inputs before its first tile
         const uint32_t sbit = 1u << (uint32_t)(st - s->steps.data());
         if (!(j.waited & sbit)) {
-            if (hipStreamWaitEvent(st->stream, j.copied, 0) != hipSuccess) s->sticky = KNNF_EDEVICE;
+            if (hipStreamWaitEvent(st->stream, j.copied, 0) != hipSuccess)
+                server_fail(s, "server: stream wait");
             j.waited |= sbit;
         }
         knnf::WorkItem w;
@@ -371,7 +387,10 @@ bool launch_step(knnf_server* s) {
     } else {
         rc = knnf::launch_items(s->ctx, items.data(), (int)items.size(), s->plan, st->stream);
     }
-    if (rc != KNNF_OK || hipEventRecord(st->done, st->stream) != hipSuccess) s->sticky = KNNF_EDEVICE;
+    if (rc == KNNF_EDEVICE || hipEventRecord(st->done, st->stream) != hipSuccess)
+        server_fail(s, "server: step launch");
+    else if (rc != KNNF_OK)
+        s->sticky = rc;
     st->active = true;
     return true;
 }
@@ -406,6 +425,8 @@ knnf_status knnf_server_create(knnf_server** out, knnf_ctx* ctx, void* pool, siz
                                const knnf_server_opts* opts) {
     if (!out || !ctx || !pool || pool_bytes < 4096)
         return knnf::set_error(KNNF_EINVAL, "knnf_server_create: bad arguments");
+    const knnf_status cs = knnf::ctx_status(ctx);
+    if (cs != KNNF_OK) return cs;
     if ((uintptr_t)pool & 255)
         return knnf::set_error(KNNF_EINVAL, "knnf_server_create: pool not 256-byte aligned");
     *out = nullptr;
@@ -431,6 +452,10 @@ knnf_status knnf_server_create(knnf_server** out, knnf_ctx* ctx, void* pool, siz
     s->pool = (char*)pool;
     s->opts = o;
     s->plan = p;
+    // server frames are checked on the host at submission (the device check
+    // would make every step synchronous)
+    s->check_inputs = !(p.flags & KNNF_PLAN_NO_INPUT_CHECK);
+    s->plan.flags |= KNNF_PLAN_NO_INPUT_CHECK;
     int prev = 0;
     hipGetDevice(&prev);
     hipSetDevice(s->device);
@@ -486,6 +511,13 @@ knnf_status knnf_server_submit(knnf_server* s, const knnf_host_frame* f, uint64_
     v.out_class = (int32_t*)1;
     knnf_status st = knnf::validate_frame(&v, 0);
     if (st != KNNF_OK) return st;
+    st = knnf::ctx_status(s->ctx);
+    if (st != KNNF_OK) return st;
+    if (s->check_inputs) {
+        const size_t px = (size_t)f->H * (size_t)f->W;
+        if (has_nonfinite(f->pc1, px) || has_nonfinite(f->prob, px * (size_t)f->C))
+            return knnf::set_error(KNNF_EINVAL, "non-finite value in the pc1 or prob input");
+    }
     const size_t bytes = knnf_frame_bytes(f->H, f->W, f->C, f->K, f->with_nbr ? 1 : 0);
     const void* m1 = nullptr;
     const void* m2 = nullptr;
@@ -530,7 +562,7 @@ knnf_status knnf_server_poll(knnf_server* s, uint64_t ticket, knnf_ticket_info* 
     info->t_launch = j.t_launch;
     info->t_done = j.t_done;
     if (s->sticky != KNNF_OK) return knnf::set_error(s->sticky, "server failed");
-    return KNNF_OK;
+    return knnf::ctx_status(s->ctx);
 }
 
 knnf_status knnf_server_result(knnf_server* s, uint64_t ticket, knnf_frame* view) {
@@ -563,6 +595,8 @@ knnf_status knnf_server_drain(knnf_server* s, double timeout_s) {
         {
             std::lock_guard<std::mutex> lk(s->mu);
             if (s->sticky != KNNF_OK) return knnf::set_error(s->sticky, "server failed");
+            const knnf_status cs = knnf::ctx_status(s->ctx);
+            if (cs != KNNF_OK) return cs;
             if (s->unfinished == 0) return KNNF_OK;
         }
         if (timeout_s > 0 && now_s() - t0 > timeout_s)

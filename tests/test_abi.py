@@ -38,7 +38,8 @@ def test_struct_layout_matches_header():
     # knnf_frame: 5 int32 + float, then 6 pointers (8-byte aligned) = 24 + 48
     assert ctypes.sizeof(_lib.knnf_frame) == 72
     assert _lib.knnf_frame.pc1.offset == 24
-    assert ctypes.sizeof(_lib.knnf_plan) == 20
+    assert ctypes.sizeof(_lib.knnf_plan) == 28
+    assert _lib.knnf_plan.flags.offset == 24
 
 
 def test_version(lib):
@@ -118,3 +119,26 @@ def test_svm_validation(lib, kw, word):
                       a["A"], a["B"], a["out"], None)
     assert st == _lib.KNNF_EINVAL
     assert word in _lib.last_error()
+
+
+def test_context_calls_reject_null(lib):
+    assert lib.knnf_ctx_status(None) == _lib.KNNF_EINVAL
+    assert lib.knnf_inject_fault(None) == _lib.KNNF_EINVAL
+    f = _frame()
+    p = _lib.knnf_plan()
+    assert lib.knnf_tune_lookup(None, ctypes.byref(f), 1, ctypes.byref(p)) == _lib.KNNF_EINVAL
+    assert lib.knnf_tune(None, ctypes.byref(f), 1, 1, None, None) == _lib.KNNF_EINVAL
+
+
+def test_create_without_a_gpu_is_a_device_error(lib):
+    """No usable HIP device: knnf_create fails with KNNF_EDEVICE (or EINVAL for
+    an ordinal beyond the devices present) and leaves *out NULL."""
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    h = ctypes.c_void_p(0x1234)
+    st = lib.knnf_create(ctypes.byref(h), 0)
+    assert st in (_lib.KNNF_EDEVICE, _lib.KNNF_EINVAL)
+    assert h.value is None
+    assert _lib.last_error() != ""
