@@ -382,6 +382,24 @@ knnf_status knnf_pc1(knnf_ctx* ctx, const float* cube, int64_t npix, int32_t ban
                      const double* mean, const double* vec, float* out, int32_t normalize,
                      void* stream);
 
+/*
+ * knnf_pc1 without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels and results as knnf_pc1, but its
+ * workspace is a static scratch array that each device holds for the life of
+ * the process (8 MiB + 16 KiB), so the call never allocates or synchronises.
+ * Limit: with normalize != 0, npix <= KNNF_PC1_NOALLOC_MAX_PIXELS (larger:
+ * KNNF_EINVAL, nothing enqueued); the raw projection uses no scratch.  Every
+ * call on one device shares that device's scratch (nothing in it needs to
+ * start at zero): calls that overlap on one GPU -- on different streams, or
+ * from several contexts or threads -- race and must be serialised by the
+ * caller, e.g. issued on one stream.
+ */
+#define KNNF_PC1_NOALLOC_MAX_PIXELS (1 << 20)
+knnf_status knnf_pc1_noalloc(knnf_ctx* ctx, const float* cube, int64_t npix, int32_t bands,
+                             const double* mean, const double* vec, float* out,
+                             int32_t normalize, void* stream);
+
 /* ---- SVM probabilities: the maps the filter averages ---------------------
  *
  * The classification stage of the one-vs-one SVM of Sec. II.C.1 (GPU

@@ -134,6 +134,8 @@ _SIGS = {
     "knnf_server_destroy": (_I, [_P]),
     "knnf_version": (ctypes.c_char_p, []),
     "knnf_pc1": (_I, [_P, _P, ctypes.c_int64, ctypes.c_int32, _P, _P, _P, ctypes.c_int32, _P]),
+    "knnf_pc1_noalloc": (_I, [_P, _P, ctypes.c_int64, ctypes.c_int32, _P, _P, _P, ctypes.c_int32,
+                              _P]),
     "knnf_svm": (_I, [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P,
                       _P]),
 }
@@ -318,6 +320,16 @@ def knnf_pc1(ctx: int, cube_ptr: int, npix: int, bands: int, mean_ptr: int, vec_
     """PC1 projection of a device cube (see include/knnf.h); device pointers."""
     check(load().knnf_pc1(ctx, cube_ptr, int(npix), int(bands), mean_ptr, vec_ptr, out_ptr,
                           1 if normalize else 0, stream))
+
+
+KNNF_PC1_NOALLOC_MAX_PIXELS = 1 << 20
+
+
+def knnf_pc1_noalloc(ctx: int, cube_ptr: int, npix: int, bands: int, mean_ptr: int, vec_ptr: int,
+                     out_ptr: int, normalize: bool = True, stream: int = 0) -> None:
+    """knnf_pc1 on the library's static scratch: allocates nothing (see include/knnf.h)."""
+    check(load().knnf_pc1_noalloc(ctx, cube_ptr, int(npix), int(bands), mean_ptr, vec_ptr,
+                                  out_ptr, 1 if normalize else 0, stream))
 
 
 def knnf_svm(ctx: int, cube_ptr: int, npix: int, bands: int, classes: int, w_ptr: int,

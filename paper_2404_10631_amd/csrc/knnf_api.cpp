@@ -129,6 +129,8 @@ struct knnf_ctx {
     std::mutex tune_mu;
     std::map<std::string, TunedPlan> tuned;
     std::string tune_path;
+    // knnf_pc1_noalloc's static scratch on this device (device address)
+    void* pc1_scratch = nullptr;
 };
 
 namespace {
@@ -576,6 +578,7 @@ knnf_status knnf_create(knnf_ctx** out, int device) {
         std::memset(c->check_host, 0, kCheckSlots * sizeof(uint32_t));
         e = hipHostGetDevicePointer((void**)&c->check_dev, c->check_host, 0);
     }
+    if (e == hipSuccess) e = (hipError_t)knnf::pc1_scratch_init(device, &c->pc1_scratch);
     hipSetDevice(prev);
     if (e != hipSuccess) {
         knnf_destroy(c);
@@ -736,6 +739,38 @@ knnf_status knnf_pc1(knnf_ctx* ctx, const float* cube, int64_t npix, int32_t ban
     const int rc = knnf::launch_pc1(cube, npix, bands, mean, vec, out, ws, pairs, ctx->num_cu,
                                     stream);
     if (rc != 0) return ctx_fail(ctx, (hipError_t)rc, "knnf_pc1 launch");
+    return KNNF_OK;
+}
+
+knnf_status knnf_pc1_noalloc(knnf_ctx* ctx, const float* cube, int64_t npix, int32_t bands,
+                             const double* mean, const double* vec, float* out,
+                             int32_t normalize, void* stream) {
+    if (npix < 1 || npix > KNNF_PC1_MAX_PIXELS)
+        return fail(KNNF_EINVAL, "knnf_pc1_noalloc: npix %lld outside [1, 2^40]", (long long)npix);
+    if (normalize && npix > KNNF_PC1_NOALLOC_MAX_PIXELS)
+        return fail(KNNF_EINVAL, "knnf_pc1_noalloc: npix %lld exceeds the static scratch (%d pixels)",
+                    (long long)npix, KNNF_PC1_NOALLOC_MAX_PIXELS);
+    if (bands < 1 || bands > KNNF_PC1_MAX_BANDS)
+        return fail(KNNF_EINVAL, "knnf_pc1_noalloc: bands %d outside [1, %d]", bands,
+                    KNNF_PC1_MAX_BANDS);
+    if (!cube || !mean || !vec || !out) return fail(KNNF_EINVAL, "knnf_pc1_noalloc: NULL pointer");
+    if (!ctx) return fail(KNNF_EINVAL, "knnf_pc1_noalloc: NULL context");
+    knnf_status st = ctx_check(ctx);
+    if (st != KNNF_OK) return st;
+    int prev = 0;
+    hipGetDevice(&prev);
+    if (prev != ctx->device) hipSetDevice(ctx->device);
+    struct Restore {
+        int prev, dev;
+        ~Restore() { if (prev != dev) hipSetDevice(prev); }
+    } restore{prev, ctx->device};
+    // the scratch's device address from context creation, never the array's name
+    char* base = (char*)ctx->pc1_scratch;
+    double* pairs = (double*)base;
+    double* ws = normalize ? (double*)(base + knnf::pc1_scratch_head()) : nullptr;
+    const int rc = knnf::launch_pc1(cube, npix, bands, mean, vec, out, ws, pairs, ctx->num_cu,
+                                    stream);
+    if (rc != 0) return ctx_fail(ctx, (hipError_t)rc, "knnf_pc1_noalloc launch");
     return KNNF_OK;
 }
 

@@ -80,6 +80,12 @@ int pc1_max_blocks();
 int launch_pc1(const float* cube, int64_t npix, int bands, const double* mean, const double* vec,
                float* out, double* ws, double* pairs, int num_cu, void* stream);
 
+// Device address of knnf_pc1_noalloc's static scratch on `device` (which must
+// be current): looked up once per device; returns hipError_t as int.  The
+// pairs occupy the first pc1_scratch_head() bytes, the projection the rest.
+int pc1_scratch_init(int device, void** ptr);
+size_t pc1_scratch_head();
+
 // SVM probability stage (defined in knnf_svm.hip), 2 <= classes <= 8.
 int launch_svm(const float* cube, int64_t npix, int bands, int classes, const double* w,
                const double* bias, const double* A, const double* B, float* out, void* stream);

@@ -25,6 +25,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
+#include "../../include/knnf.h"
 #include "knnf_device.h"
 
 namespace knnf {
@@ -217,6 +220,37 @@ pc1_normalise(const double* __restrict__ ws, int64_t npix, const double* __restr
 }  // namespace
 
 int pc1_max_blocks() { return PC1_MAX_BLOCKS; }
+
+// ---- Static scratch of knnf_pc1_noalloc: the projection blocks' (min, max)
+// pairs, then the binary64 projection of up to KNNF_PC1_NOALLOC_MAX_PIXELS
+// pixels.  Each device holds its own copy for the life of the process; host
+// code uses the device address hipGetSymbolAddress reports for it (the
+// array's name is a host-side stand-in, not a device address).
+constexpr size_t kScratchHead = 16384;
+static_assert(2 * PC1_MAX_BLOCKS * sizeof(double) <= kScratchHead, "pairs fit the scratch head");
+constexpr size_t kScratchBytes = kScratchHead + sizeof(double) * (size_t)KNNF_PC1_NOALLOC_MAX_PIXELS;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::once_flag g_scratch_once[kMaxDevices];
+void* g_scratch_ptr[kMaxDevices];
+hipError_t g_scratch_err[kMaxDevices];
+}  // namespace
+
+int pc1_scratch_init(int device, void** ptr) {
+    *ptr = nullptr;
+    if (device < 0 || device >= kMaxDevices) return (int)hipErrorInvalidDevice;
+    // once per device, with that device current (the caller sets it)
+    std::call_once(g_scratch_once[device], [device] {
+        g_scratch_err[device] = hipGetSymbolAddress(&g_scratch_ptr[device], HIP_SYMBOL(scratch));
+        if (g_scratch_err[device] != hipSuccess) g_scratch_ptr[device] = nullptr;
+    });
+    *ptr = g_scratch_ptr[device];
+    return (int)g_scratch_err[device];
+}
+
+size_t pc1_scratch_head() { return kScratchHead; }
 
 int launch_pc1(const float* cube, int64_t npix, int bands, const double* mean, const double* vec,
                float* out, double* ws, double* pairs, int num_cu, void* stream) {
