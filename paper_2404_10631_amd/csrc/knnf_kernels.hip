@@ -337,10 +337,12 @@ __device__ __forceinline__ uint64_t flush_query(TileState<QR, QC>& S, const Fram
 // >= 0 and binary32 rounding is monotone, so fmaf(b, b, a2) with the smallest
 // |b| and a2 of a set of candidates bounds all their distances from below;
 // a set whose bound exceeds every query's current bound tau cannot hold a
-// neighbour.  The scan visits the window in patches of PR rows x 64/PR
-// columns (the window chunk, PR = 2^lpr = 8, 16 or 32): lane L holds row
-// blk + (L % PR), column jc + L / PR, so a lane's row term stays fixed while a
-// row block is swept outward column step by column step.
+// neighbour.  The scan visits the window in patches of PR rows x SW = 64/PR
+// columns (the window chunk): PR is the tile's number of live rows, capped at
+// 2^lpr (8, 16, 32 or 64), so that a patch holds no dead rows when the live
+// rows fit one patch.  Lane L holds row blk + (L % PR), column jc + L / PR
+// (lanes with L / PR >= SW hold nothing), so a lane's row term stays fixed
+// while a row block is swept outward column step by column step.
 //   * live rows: rows where some query's row term alone is within its bound
 //     (its own column has b = 0);
 //   * per block of 16 live rows: the tile's own column steps, then steps to
@@ -392,9 +394,11 @@ __device__ __forceinline__ void scan_pruned(TileState<QR, QC>& S, const FrameDes
         }
     }
 
-    const int PR = 1 << lpr, lsw = 6 - lpr, SW = 1 << lsw;  // patch rows, step columns
-    const int lr = L & (PR - 1), lc = L >> lpr;
-    const int ncen = (nqc + SW - 1) >> lsw;  // steps over the tile's own columns
+    const int PR = max(1, min(1 << lpr, hi - lo + 1));  // patch rows (uniform)
+    const int SW = WAVE / PR;                            // patch columns (step width)
+    const int lc = L / PR, lr = L - lc * PR;
+    const bool lane_ok = lc < SW;
+    const int ncen = (nqc + SW - 1) / SW;  // steps over the tile's own columns
     for (int blk = lo; blk <= hi; blk += PR) {
         const int bhi = min(blk + PR - 1, hi);
         const int i = blk + lr;
@@ -451,7 +455,7 @@ __device__ __forceinline__ void scan_pruned(TileState<QR, QC>& S, const FrameDes
             const float ip = ipn;
             if (st + 1 < ns) ipn = rowp[min(max(step_col(st + 1) + lc, 0), W - 1)];
             const int j = jc + lc;
-            const bool jok = j >= 0 && j < W;
+            const bool jok = lane_ok && j >= 0 && j < W;
             const uint32_t idx = (uint32_t)i * (uint32_t)W + (uint32_t)j;
             float b[QC];
 #pragma unroll
@@ -621,14 +625,13 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
         }
         if (lp == 0) S.iq[sq] = iqs;
         seg_sort_u32<E>(x, lp);
+        // the segment's element K - 1 (lane (K-1) / E, register (K-1) % E) is
+        // the bound; only that lane writes it
+        const int uk = (K - 1) % E;
+        uint32_t dk = x[0];
 #pragma unroll
-        for (int u = 0; u < E; ++u) S.list[sq][lp * E + u] = x[u];
-        wave_sync();
-        if (L < Q) {
-            const bool ok = (L / QC) < nqr && (L % QC) < nqc;
-            const uint32_t dk = S.list[L][K - 1];
-            S.tauhi[L] = ok ? dk : 0u;
-        }
+        for (int u = 1; u < E; ++u) dk = u == uk ? x[u] : dk;
+        if (lp == (K - 1) / E) S.tauhi[sq] = sok ? dk : 0u;
         wave_sync();
     }
 
@@ -888,12 +891,24 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
             }
         }
         const size_t pix = (size_t)(r0 + sqr) * W + c0 + sqc;
+        if (own && lp * E < K) {
+            // the lane's E neighbours go to the list as 16-byte stores (entries
+            // from K on are never read); a slot without a candidate gathers
+            // the query's own row (see flush_query)
+#pragma unroll
+            for (int u = 0; u < E; u += 4) {
+                uint4 v;
+                v.x = y[u] == KEY_INF ? (uint32_t)pix : (uint32_t)y[u];
+                v.y = y[u + 1] == KEY_INF ? (uint32_t)pix : (uint32_t)y[u + 1];
+                v.z = y[u + 2] == KEY_INF ? (uint32_t)pix : (uint32_t)y[u + 2];
+                v.w = y[u + 3] == KEY_INF ? (uint32_t)pix : (uint32_t)y[u + 3];
+                *(uint4*)&S.list[sq][lp * E + u] = v;
+            }
+        }
 #pragma unroll
         for (int u = 0; u < E; ++u) {
             const int e = lp * E + u;
             if (own && e < K) {
-                // a slot without a candidate gathers the query's own row (see flush_query)
-                S.list[sq][e] = y[u] == KEY_INF ? (uint32_t)pix : (uint32_t)y[u];
                 if (f.out_nbr) f.out_nbr[pix * K + e] = (int32_t)(uint32_t)y[u];
                 if (f.out_dist) f.out_dist[pix * K + e] = __uint_as_float((uint32_t)(y[u] >> 32));
             }
