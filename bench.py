@@ -47,10 +47,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
-    ap.add_argument("--legs", default="plain,batch,serve,pc1,svm,variants",
+    ap.add_argument("--legs", default="plain,batch,serve,pc1,svm,fused,variants",
                     help="comma list of: plain (headline), batch (uneven / small-frame "
                          "batches), serve (Poisson mixed stream), pc1 (the projection "
-                         "step that produces the band), svm (the probability maps), "
+                         "step that produces the band), svm (the probability maps), fused "
+                         "(both from one read of the cube), "
                          "variants (whole-frame window, lambda = 0)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (to scale HBM counters)")
@@ -261,6 +262,63 @@ def svm_leg(ctx, stream, reps=20):
     out["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                        "frac": round(gbs / PEAK_HBM_GBS, 4),
                        "traffic": (rec or {}).get("traffic_bytes_per_call")}
+    return out
+
+
+def fused_leg(ctx, stream, reps=20):
+    """Both steps before the filter from one read of the cube (knnf_svm_pc1:
+    four-class SVM maps and the normalised PC1 band) against the two separate
+    calls (knnf_svm + knnf_pc1), on the brain-like W480 x H380 x 128 and the
+    dermatology-like 1000 x 1000 x 100 cube; HBM-bound."""
+    import torch
+
+    from paper_2404_10631_amd import _lib, inputs
+
+    out = {}
+    for key, (H, W, B, kind) in (("brain", (380, 480, 128, "brain")),
+                                 ("derma", (1000, 1000, 100, "derma"))):
+        cube, mean, vec = inputs.g_cube(H, W, B, 1, kind)
+        model = [torch.from_numpy(a).cuda() for a in inputs.g_svm_model(4, B, 2)]
+        dcube = torch.from_numpy(cube).cuda()
+        dmean = torch.from_numpy(mean).cuda()
+        dvec = torch.from_numpy(vec).cuda()
+        del cube
+        npix = H * W
+        maps = torch.empty((npix, 4), dtype=torch.float32, device="cuda")
+        band = torch.empty(npix, dtype=torch.float32, device="cuda")
+        mp = [t.data_ptr() for t in model]
+
+        def fused():
+            _lib.knnf_svm_pc1(ctx, dcube.data_ptr(), npix, B, 4, *mp, dmean.data_ptr(),
+                              dvec.data_ptr(), maps.data_ptr(), band.data_ptr(), True, stream)
+
+        def separate():
+            _lib.knnf_svm(ctx, dcube.data_ptr(), npix, B, 4, *mp, maps.data_ptr(), stream)
+            _lib.knnf_pc1(ctx, dcube.data_ptr(), npix, B, dmean.data_ptr(), dvec.data_ptr(),
+                          band.data_ptr(), True, stream)
+
+        res = {}
+        for name, fn in (("fused", fused), ("separate", separate)):
+            fn()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()  # on torch's current stream, the one the launches use
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            res[name] = e0.elapsed_time(e1) / reps
+        # algorithmic bytes of the fused call: the cube once, the maps and the
+        # band written, the binary64 projection written and read back once for
+        # the normalisation, the model, band averages and eigenvector once
+        nbytes = npix * B * 4 + npix * 16 + npix * 4 + npix * 16 + 6 * (B + 3) * 8 + 2 * B * 8
+        gbs = nbytes / (res["fused"] * 1e-3) / 1e9
+        out[key] = {"workload": f"{kind}-like cube W{W}xH{H}, {B} bands, 4 classes, normalised band",
+                    "fused_ms": round(res["fused"], 5), "separate_ms": round(res["separate"], 5),
+                    "speedup": round(res["separate"] / res["fused"], 3), "bytes": nbytes,
+                    "GB_per_s": round(gbs, 1), "frac_of_hbm_peak": round(gbs / PEAK_HBM_GBS, 4)}
+        del dcube, maps, band
     return out
 
 
@@ -566,6 +624,9 @@ def main():
     if "svm" in legs:
         print("bench: svm leg", file=sys.stderr, flush=True)
         out["svm_probabilities"] = svm_leg(ctx, stream)
+    if "fused" in legs:
+        print("bench: fused svm + pc1 leg", file=sys.stderr, flush=True)
+        out["svm_pc1_fused"] = fused_leg(ctx, stream)
     if not args.no_cpu:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(spec, pc1, prob, args.cpu_seconds)

@@ -439,6 +439,27 @@ knnf_status knnf_svm(knnf_ctx* ctx, const float* cube, int64_t npix, int32_t ban
                      int32_t classes, const double* w, const double* bias, const double* A,
                      const double* B, float* out, void* stream);
 
+/* ---- Both steps before the filter from one read of the cube ------------
+ *
+ * knnf_svm and knnf_pc1 of the same cube in one pass over it: the kernel that
+ * computes the SVM probability maps also accumulates each pixel's PC1
+ * projection from the same staged bands (the pipeline's classification and
+ * dimensionality-reduction steps, Sec. II.C.1-2, read the image once instead
+ * of twice).  out_prob is knnf_svm's output (bitwise the same); out_band is
+ * knnf_pc1's (normalize as there; the projection is summed band by band in
+ * ascending order, so it can differ from knnf_pc1's, whose summation order is
+ * different, by the last binary32 bit).  Arguments, layouts and limits as in
+ * those two calls; `cube` must hold both steps' input.  With normalize != 0
+ * it uses the context workspace of knnf_pc1 (8 B per pixel plus 16 B per 256
+ * pixels; growing it synchronizes the device and allocates).  Asynchronous on
+ * `stream`.  Errors: as knnf_svm, plus KNNF_EINVAL for NULL mean, vec or
+ * out_band, KNNF_ENOMEM if the workspace cannot grow.
+ */
+knnf_status knnf_svm_pc1(knnf_ctx* ctx, const float* cube, int64_t npix, int32_t bands,
+                         int32_t classes, const double* w, const double* bias, const double* A,
+                         const double* B, const double* mean, const double* vec, float* out_prob,
+                         float* out_band, int32_t normalize, void* stream);
+
 /* Text of the last error on the calling thread ("" if none). */
 const char* knnf_last_error(void);
 

@@ -138,6 +138,8 @@ _SIGS = {
                               _P]),
     "knnf_svm": (_I, [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P,
                       _P]),
+    "knnf_svm_pc1": (_I, [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P,
+                          _P, _P, _P, _P, ctypes.c_int32, _P]),
 }
 
 _lib = None
@@ -337,3 +339,12 @@ def knnf_svm(ctx: int, cube_ptr: int, npix: int, bands: int, classes: int, w_ptr
     """SVM probability maps of a device cube (see include/knnf.h); device pointers."""
     check(load().knnf_svm(ctx, cube_ptr, int(npix), int(bands), int(classes), w_ptr, bias_ptr,
                           a_ptr, b_ptr, out_ptr, stream))
+
+
+def knnf_svm_pc1(ctx: int, cube_ptr: int, npix: int, bands: int, classes: int, w_ptr: int,
+                 bias_ptr: int, a_ptr: int, b_ptr: int, mean_ptr: int, vec_ptr: int,
+                 prob_ptr: int, band_ptr: int, normalize: bool = True, stream: int = 0) -> None:
+    """SVM maps and the PC1 band from one read of a device cube (see include/knnf.h)."""
+    check(load().knnf_svm_pc1(ctx, cube_ptr, int(npix), int(bands), int(classes), w_ptr, bias_ptr,
+                              a_ptr, b_ptr, mean_ptr, vec_ptr, prob_ptr, band_ptr,
+                              1 if normalize else 0, stream))

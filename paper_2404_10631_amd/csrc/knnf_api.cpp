@@ -801,6 +801,62 @@ knnf_status knnf_svm(knnf_ctx* ctx, const float* cube, int64_t npix, int32_t ban
     return KNNF_OK;
 }
 
+knnf_status knnf_svm_pc1(knnf_ctx* ctx, const float* cube, int64_t npix, int32_t bands,
+                         int32_t classes, const double* w, const double* bias, const double* A,
+                         const double* B, const double* mean, const double* vec, float* out_prob,
+                         float* out_band, int32_t normalize, void* stream) {
+    if (npix < 1 || npix > KNNF_SVM_MAX_PIXELS)
+        return fail(KNNF_EINVAL, "knnf_svm_pc1: npix %lld outside [1, 2^31]", (long long)npix);
+    if (bands < 1 || bands > KNNF_SVM_MAX_BANDS)
+        return fail(KNNF_EINVAL, "knnf_svm_pc1: bands %d outside [1, %d]", bands, KNNF_SVM_MAX_BANDS);
+    if (classes < 2 || classes > KNNF_SVM_MAX_CLASSES)
+        return fail(KNNF_EINVAL, "knnf_svm_pc1: classes %d outside [2, %d]", classes,
+                    KNNF_SVM_MAX_CLASSES);
+    if (!cube || !w || !bias || !A || !B || !mean || !vec || !out_prob || !out_band)
+        return fail(KNNF_EINVAL, "knnf_svm_pc1: NULL pointer");
+    if (!ctx) return fail(KNNF_EINVAL, "knnf_svm_pc1: NULL context");
+    knnf_status st = ctx_check(ctx);
+    if (st != KNNF_OK) return st;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    int prev = 0;
+    hipGetDevice(&prev);
+    if (prev != ctx->device) hipSetDevice(ctx->device);
+    struct Restore {
+        int prev, dev;
+        ~Restore() { if (prev != dev) hipSetDevice(prev); }
+    } restore{prev, ctx->device};
+    double* pairs = nullptr;
+    double* ws = nullptr;
+    if (normalize) {
+        // workspace: one (min, max) pair per kernel block, then the binary64
+        // projection (shared with knnf_pc1; grows like it)
+        const int64_t nb = (npix + knnf::svm_pixels_per_block() - 1) / knnf::svm_pixels_per_block();
+        const size_t head = ((size_t)nb * 2 * sizeof(double) + 255) & ~size_t(255);
+        const size_t need = head + (size_t)npix * sizeof(double);
+        if (ctx->pc1_ws_bytes < need) {
+            hipError_t e = hipDeviceSynchronize();
+            if (e != hipSuccess) return ctx_fail(ctx, e, "knnf_svm_pc1: synchronize");
+            const size_t bytes = std::max(need, ctx->pc1_ws_bytes * 2);
+            if (ctx->pc1_ws) hipFree(ctx->pc1_ws);
+            ctx->pc1_ws = nullptr;
+            ctx->pc1_ws_bytes = 0;
+            e = hipMalloc((void**)&ctx->pc1_ws, bytes);
+            if (e != hipSuccess)
+                return fail(KNNF_ENOMEM, "knnf_svm_pc1 workspace: %s", hipGetErrorString(e));
+            ctx->pc1_ws_bytes = bytes;
+        }
+        pairs = (double*)ctx->pc1_ws;
+        ws = (double*)(ctx->pc1_ws + head);
+    }
+    int nblocks = 0;
+    int rc = knnf::launch_svm_pc1(cube, npix, bands, classes, w, bias, A, B, mean, vec, out_prob,
+                                  out_band, ws, pairs, &nblocks, stream);
+    if (rc == 0 && normalize)
+        rc = knnf::launch_pc1_normalise(ws, npix, pairs, nblocks, out_band, ctx->num_cu, stream);
+    if (rc != 0) return ctx_fail(ctx, (hipError_t)rc, "knnf_svm_pc1 launch");
+    return KNNF_OK;
+}
+
 knnf_status knnf_stats_enable(knnf_ctx* ctx, int on) {
     if (!ctx) return fail(KNNF_EINVAL, "knnf_stats_enable: NULL context");
     knnf_status st = ctx_check(ctx);

@@ -86,8 +86,23 @@ int launch_pc1(const float* cube, int64_t npix, int bands, const double* mean, c
 int pc1_scratch_init(int device, void** ptr);
 size_t pc1_scratch_head();
 
+// Normalisation launch of the PC1 step alone: out[p] = (ws[p] - min) / (max -
+// min) with min and max reduced from npairs (min, max) pairs.
+int launch_pc1_normalise(const double* ws, int64_t npix, const double* pairs, int npairs,
+                         float* out, int num_cu, void* stream);
+
 // SVM probability stage (defined in knnf_svm.hip), 2 <= classes <= 8.
 int launch_svm(const float* cube, int64_t npix, int bands, int classes, const double* w,
                const double* bias, const double* A, const double* B, float* out, void* stream);
+
+// SVM maps and the PC1 projection from one read of the cube: `out` as
+// launch_svm; the projection goes to band (binary32, ws == nullptr) or to ws
+// (binary64) with each block's (min, max) in pairs[2 * block ..], for
+// launch_pc1_normalise.  Returns the number of blocks through *nblocks.
+int svm_pixels_per_block();
+int launch_svm_pc1(const float* cube, int64_t npix, int bands, int classes, const double* w,
+                   const double* bias, const double* A, const double* B, const double* mean,
+                   const double* vec, float* out, float* band, double* ws, double* pairs,
+                   int* nblocks, void* stream);
 
 }  // namespace knnf

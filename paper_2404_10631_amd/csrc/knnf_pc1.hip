@@ -221,6 +221,15 @@ pc1_normalise(const double* __restrict__ ws, int64_t npix, const double* __restr
 
 int pc1_max_blocks() { return PC1_MAX_BLOCKS; }
 
+int launch_pc1_normalise(const double* ws, int64_t npix, const double* pairs, int npairs,
+                         float* out, int num_cu, void* stream) {
+    const int64_t nb = (npix + PC1_THREADS - 1) / PC1_THREADS;
+    const int nblocks = (int)(nb < (int64_t)num_cu ? nb : (int64_t)num_cu);
+    hipLaunchKernelGGL(pc1_normalise, dim3(nblocks), dim3(PC1_THREADS), 0, (hipStream_t)stream, ws,
+                       npix, pairs, npairs, out);
+    return (int)hipGetLastError();
+}
+
 // ---- Static scratch of knnf_pc1_noalloc: the projection blocks' (min, max)
 // pairs, then the binary64 projection of up to KNNF_PC1_NOALLOC_MAX_PIXELS
 // pixels.  Each device holds its own copy for the life of the process; host

@@ -26,6 +26,9 @@
 // became scalar loads whose waits lay on every wave's critical path) and for
 // the coupling iteration, whose sweep count differs from pixel to pixel.
 // The loads of the next chunk are in flight while the current one is used.
+// The fused variant (PC1 = true) also accumulates the PC1 projection from the
+// same chunks, so the pipeline's two steps before the filter read the cube
+// once.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -48,15 +51,45 @@ __device__ __forceinline__ constexpr int pair_index(int i, int j) {
     return i * C - i * (i + 1) / 2 + (j - i - 1);
 }
 
-template <int C, bool VEC>
+// Block-wide (min, max) of per-thread values -> pairs[2 * blockIdx.x ..].
+__device__ void svm_publish_minmax(double lo, double hi, double* pairs) {
+    __shared__ double slo[SVM_THREADS / 64], shi[SVM_THREADS / 64];
+    for (int m = 1; m < 64; m <<= 1) {
+        lo = fmin(lo, __shfl_xor(lo, m));
+        hi = fmax(hi, __shfl_xor(hi, m));
+    }
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        slo[wv] = lo;
+        shi[wv] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < SVM_THREADS / 64; ++k) {
+            lo = fmin(lo, slo[k]);
+            hi = fmax(hi, shi[k]);
+        }
+        pairs[2 * blockIdx.x] = lo;
+        pairs[2 * blockIdx.x + 1] = hi;
+    }
+}
+
+// PC1 = true also accumulates the PC1 projection of each pixel (Sec. II.C.2:
+// the cube centred by the band averages, times the first eigenvector),
+// band by band in ascending order in binary64, from the same staged chunks:
+// the step before the filter reads the cube once for both of its outputs.
+template <int C, bool VEC, bool PC1>
 __global__ void __launch_bounds__(SVM_THREADS)
 svm_prob_kernel(const float* __restrict__ cube, int64_t npix, int bands,
                 const double* __restrict__ w, const double* __restrict__ bias,
                 const double* __restrict__ A, const double* __restrict__ B,
-                float* __restrict__ out) {
+                float* __restrict__ out, const double* __restrict__ mean,
+                const double* __restrict__ vec, float* __restrict__ band,
+                double* __restrict__ ws, double* __restrict__ pairs) {
     constexpr int M = C * (C - 1) / 2;
     __shared__ __attribute__((aligned(16))) float tile[SVM_THREADS * SVM_STRIDE];
-    constexpr int NWT = M * SVM_CHUNK;                        // weights of one chunk
+    // weights of one chunk: the M hyperplanes, then (PC1) averages and eigenvector
+    constexpr int NWT = (M + (PC1 ? 2 : 0)) * SVM_CHUNK;
     constexpr int NW = (NWT + SVM_THREADS - 1) / SVM_THREADS;  // per thread
     __shared__ __attribute__((aligned(16))) double wl[NWT];
     const int tid = threadIdx.x;
@@ -67,6 +100,7 @@ svm_prob_kernel(const float* __restrict__ cube, int64_t npix, int bands,
     double f[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) f[m] = 0.0;
+    double pj = 0.0;  // PC1 projection
     const float* row = tile + tid * SVM_STRIDE;
     // Staging of cube[first .. first+255][c0 .. c0+31] (rows past the frame
     // repeat its last pixel, bands past the cube read as 0).  The next chunk
@@ -95,8 +129,12 @@ svm_prob_kernel(const float* __restrict__ cube, int64_t npix, int bands,
 #pragma unroll
         for (int i = 0; i < NW; ++i) {
             const int e = tid + SVM_THREADS * i;   // (m, k) = (e / 32, e % 32)
+            const int m = e / SVM_CHUNK;
             const int bb = c0 + (e % SVM_CHUNK);
-            wv[i] = (e < NWT && bb < bands) ? w[(int64_t)(e / SVM_CHUNK) * bands + bb] : 0.0;
+            double x = 0.0;
+            if (e < NWT && bb < bands)
+                x = m < M ? w[(int64_t)m * bands + bb] : (m == M ? mean[bb] : vec[bb]);
+            wv[i] = x;
         }
     };
     fetch(0);
@@ -121,10 +159,14 @@ svm_prob_kernel(const float* __restrict__ cube, int64_t npix, int bands,
                 const float4 x4 = *(const float4*)(row + 4 * k);
                 const double x[4] = {(double)x4.x, (double)x4.y, (double)x4.z, (double)x4.w};
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
+                for (int e = 0; e < 4; ++e) {
 #pragma unroll
                     for (int m = 0; m < M; ++m)
                         f[m] = fma(wl[m * SVM_CHUNK + 4 * k + e], x[e], f[m]);
+                    if constexpr (PC1)
+                        pj = fma(x[e] - wl[M * SVM_CHUNK + 4 * k + e],
+                                 wl[(M + 1) * SVM_CHUNK + 4 * k + e], pj);
+                }
             }
         } else {
             const int nb = bands - c0;
@@ -132,11 +174,23 @@ svm_prob_kernel(const float* __restrict__ cube, int64_t npix, int bands,
                 const double x = (double)row[k];
 #pragma unroll
                 for (int m = 0; m < M; ++m) f[m] = fma(wl[m * SVM_CHUNK + k], x, f[m]);
+                if constexpr (PC1)
+                    pj = fma(x - wl[M * SVM_CHUNK + k], wl[(M + 1) * SVM_CHUNK + k], pj);
             }
         }
         __syncthreads();
     }
     const int64_t pix = first + tid;
+    if constexpr (PC1) {
+        if (ws) {
+            // every thread of the block takes part (pixels past the frame add nothing)
+            const bool in = pix < npix;
+            svm_publish_minmax(in ? pj : __builtin_inf(), in ? pj : -__builtin_inf(), pairs);
+            if (in) ws[pix] = pj;
+        } else if (pix < npix) {
+            band[pix] = (float)pj;
+        }
+    }
     if (pix >= npix) return;
 
     // (ii) binary probabilities; r[m] is that of the pair's first class
@@ -212,34 +266,61 @@ svm_prob_kernel(const float* __restrict__ cube, int64_t npix, int bands,
     for (int t = 0; t < C; ++t) o[t] = (float)p[t];
 }
 
-template <int C>
-int launch_c(const float* cube, int64_t npix, int bands, const double* w, const double* bias,
-             const double* A, const double* B, float* out, void* stream) {
-    const int64_t blocks = (npix + SVM_THREADS - 1) / SVM_THREADS;
-    const bool vec = bands % 4 == 0 && ((uintptr_t)cube & 15) == 0;
+struct SvmArgs {
+    const float* cube;
+    int64_t npix;
+    int bands;
+    const double *w, *bias, *A, *B, *mean, *vec;
+    float *out, *band;
+    double *ws, *pairs;
+};
+
+template <int C, bool PC1>
+int launch_c(const SvmArgs& a, void* stream) {
+    const int64_t blocks = (a.npix + SVM_THREADS - 1) / SVM_THREADS;
+    const bool vec = a.bands % 4 == 0 && ((uintptr_t)a.cube & 15) == 0;
     if (vec)
-        hipLaunchKernelGGL((svm_prob_kernel<C, true>), dim3((uint32_t)blocks), dim3(SVM_THREADS), 0,
-                           (hipStream_t)stream, cube, npix, bands, w, bias, A, B, out);
+        hipLaunchKernelGGL((svm_prob_kernel<C, true, PC1>), dim3((uint32_t)blocks), dim3(SVM_THREADS),
+                           0, (hipStream_t)stream, a.cube, a.npix, a.bands, a.w, a.bias, a.A, a.B,
+                           a.out, a.mean, a.vec, a.band, a.ws, a.pairs);
     else
-        hipLaunchKernelGGL((svm_prob_kernel<C, false>), dim3((uint32_t)blocks), dim3(SVM_THREADS), 0,
-                           (hipStream_t)stream, cube, npix, bands, w, bias, A, B, out);
+        hipLaunchKernelGGL((svm_prob_kernel<C, false, PC1>), dim3((uint32_t)blocks), dim3(SVM_THREADS),
+                           0, (hipStream_t)stream, a.cube, a.npix, a.bands, a.w, a.bias, a.A, a.B,
+                           a.out, a.mean, a.vec, a.band, a.ws, a.pairs);
     return (int)hipGetLastError();
+}
+
+template <bool PC1>
+int launch_classes(int classes, const SvmArgs& a, void* stream) {
+    switch (classes) {
+        case 2: return launch_c<2, PC1>(a, stream);
+        case 3: return launch_c<3, PC1>(a, stream);
+        case 4: return launch_c<4, PC1>(a, stream);
+        case 5: return launch_c<5, PC1>(a, stream);
+        case 6: return launch_c<6, PC1>(a, stream);
+        case 7: return launch_c<7, PC1>(a, stream);
+        case 8: return launch_c<8, PC1>(a, stream);
+        default: return (int)hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
 
 int launch_svm(const float* cube, int64_t npix, int bands, int classes, const double* w,
                const double* bias, const double* A, const double* B, float* out, void* stream) {
-    switch (classes) {
-        case 2: return launch_c<2>(cube, npix, bands, w, bias, A, B, out, stream);
-        case 3: return launch_c<3>(cube, npix, bands, w, bias, A, B, out, stream);
-        case 4: return launch_c<4>(cube, npix, bands, w, bias, A, B, out, stream);
-        case 5: return launch_c<5>(cube, npix, bands, w, bias, A, B, out, stream);
-        case 6: return launch_c<6>(cube, npix, bands, w, bias, A, B, out, stream);
-        case 7: return launch_c<7>(cube, npix, bands, w, bias, A, B, out, stream);
-        case 8: return launch_c<8>(cube, npix, bands, w, bias, A, B, out, stream);
-        default: return (int)hipErrorInvalidValue;
-    }
+    const SvmArgs a{cube, npix, bands, w, bias, A, B, nullptr, nullptr, out, nullptr, nullptr, nullptr};
+    return launch_classes<false>(classes, a, stream);
+}
+
+int svm_pixels_per_block() { return SVM_THREADS; }
+
+int launch_svm_pc1(const float* cube, int64_t npix, int bands, int classes, const double* w,
+                   const double* bias, const double* A, const double* B, const double* mean,
+                   const double* vec, float* out, float* band, double* ws, double* pairs,
+                   int* nblocks, void* stream) {
+    *nblocks = (int)((npix + SVM_THREADS - 1) / SVM_THREADS);
+    const SvmArgs a{cube, npix, bands, w, bias, A, B, mean, vec, out, band, ws, pairs};
+    return launch_classes<true>(classes, a, stream);
 }
 
 }  // namespace knnf
