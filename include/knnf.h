@@ -125,14 +125,13 @@ typedef enum { KNNF_SEARCH_EXHAUSTIVE = 0, KNNF_SEARCH_PRUNED = 1 } knnf_search;
  *   waves         wavefronts per workgroup; 1, 2 or 4
  *   launch        knnf_launch (batched launches only)
  *   chunk_rows    window chunk of the pruned search: the candidates a
- *                 wavefront evaluates per step form a patch of P rows x
- *                 floor(64 / P) columns, P = the tile's rows still in reach of
- *                 some query's bound, at most chunk_rows: 8, 16, 32 or 64 (the
- *                 exhaustive search always sweeps 4 rows x 64 columns)
+ *                 wavefront evaluates per step form a patch of chunk_rows rows
+ *                 x (64 / chunk_rows) columns; 8, 16 or 32 (the exhaustive
+ *                 search always sweeps 4 rows x 64 columns)
  *   flags         KNNF_PLAN_* bits
  * A zero tile, wave, launch or chunk field means "the context's default"
  * (initially a pruned search with 1 x 8 tiles, one wavefront per workgroup,
- * grid launches and chunks of up to 16 rows); search and flags are always taken from
+ * grid launches and 16-row chunks); search and flags are always taken from
  * the plan (0 = exhaustive, input check on).  Every plan gives bitwise
  * identical outputs.
  */
@@ -144,7 +143,7 @@ typedef struct {
     int32_t tile_cols;
     int32_t waves;
     int32_t launch;     /* batched launches: knnf_launch                          */
-    int32_t chunk_rows; /* pruned search: cap of the window chunk rows (8 .. 64)   */
+    int32_t chunk_rows; /* pruned search: window chunk rows (8, 16, 32)           */
     int32_t flags;      /* KNNF_PLAN_* bits                                       */
 } knnf_plan;
 

@@ -170,8 +170,7 @@ bool plan_ok_impl(const knnf_plan& p) {
     if (!shape) return false;
     if (p.waves != 1 && p.waves != 2 && p.waves != 4) return false;
     if (p.launch != KNNF_LAUNCH_PERSISTENT && p.launch != KNNF_LAUNCH_GRID) return false;
-    if (p.chunk_rows != 8 && p.chunk_rows != 16 && p.chunk_rows != 32 && p.chunk_rows != 64)
-        return false;
+    if (p.chunk_rows != 8 && p.chunk_rows != 16 && p.chunk_rows != 32) return false;
     if (p.flags & ~KNNF_PLAN_NO_INPUT_CHECK) return false;
     return true;
 }
@@ -197,7 +196,7 @@ knnf::LaunchCfg to_cfg(const knnf_plan& p) {
     c.waves = p.waves;
     c.pruned = p.search == KNNF_SEARCH_PRUNED ? 1 : 0;
     c.persistent = p.launch != KNNF_LAUNCH_GRID;
-    c.chunk_log2 = p.chunk_rows == 8 ? 3 : p.chunk_rows == 16 ? 4 : p.chunk_rows == 32 ? 5 : 6;
+    c.chunk_log2 = p.chunk_rows == 8 ? 3 : (p.chunk_rows == 32 ? 5 : 4);
     return c;
 }
 
@@ -907,7 +906,7 @@ knnf_status knnf_tune(knnf_ctx* ctx, const knnf_frame* frames, int n, int reps, 
     static const int ws[] = {1, 2, 4};
     static const int ss[] = {KNNF_SEARCH_EXHAUSTIVE, KNNF_SEARCH_PRUNED};
     static const int ls[] = {KNNF_LAUNCH_PERSISTENT, KNNF_LAUNCH_GRID};
-    static const int chunks[] = {8, 16, 32, 64};
+    static const int chunks[] = {8, 16, 32};
     hipStream_t hs = (hipStream_t)stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t he = hipEventCreate(&e0);
@@ -925,7 +924,7 @@ knnf_status knnf_tune(knnf_ctx* ctx, const knnf_frame* frames, int n, int reps, 
                 for (int l : ls)
                     for (int ch : chunks) {
                         if (n == 1 && l == KNNF_LAUNCH_PERSISTENT) continue;  // single frames ignore it
-                        if (s == KNNF_SEARCH_EXHAUSTIVE && ch != 64) continue;  // no window chunk there
+                        if (s == KNNF_SEARCH_EXHAUSTIVE && ch != 16) continue;  // no window chunk there
                         knnf_plan p{};
                         p.search = s;
                         p.tile_rows = sh[0];

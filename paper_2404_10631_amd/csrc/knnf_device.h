@@ -27,7 +27,7 @@ struct LaunchCfg {
     int waves;     // wavefronts per workgroup: 1, 2, 4
     int pruned;    // 0 exhaustive, 1 pruned
     int persistent;  // batched launches: 1 persistent claim loop, 0 one wavefront per task
-    int chunk_log2;  // pruned search: log2 of the patch rows' cap (3 .. 6)
+    int chunk_log2;  // pruned search: log2 of the patch rows (3, 4, 5)
 };
 
 // Host-side launchers (defined in knnf_kernels.hip).  Return hipError_t as int.

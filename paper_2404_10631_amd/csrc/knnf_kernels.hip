@@ -338,11 +338,9 @@ __device__ __forceinline__ uint64_t flush_query(TileState<QR, QC>& S, const Fram
 // |b| and a2 of a set of candidates bounds all their distances from below;
 // a set whose bound exceeds every query's current bound tau cannot hold a
 // neighbour.  The scan visits the window in patches of PR rows x SW = 64/PR
-// columns (the window chunk): PR is the tile's number of live rows, capped at
-// 2^lpr (8, 16, 32 or 64), so that a patch holds no dead rows when the live
-// rows fit one patch.  Lane L holds row blk + (L % PR), column jc + L / PR
-// (lanes with L / PR >= SW hold nothing), so a lane's row term stays fixed
-// while a row block is swept outward column step by column step.
+// columns (the window chunk, PR = 2^lpr = 8, 16 or 32): lane L holds row
+// blk + (L % PR), column jc + L / PR, so a lane's row term stays fixed while a
+// row block is swept outward column step by column step.
 //   * live rows: rows where some query's row term alone is within its bound
 //     (its own column has b = 0);
 //   * per block of 16 live rows: the tile's own column steps, then steps to
@@ -394,11 +392,9 @@ __device__ __forceinline__ void scan_pruned(TileState<QR, QC>& S, const FrameDes
         }
     }
 
-    const int PR = max(1, min(1 << lpr, hi - lo + 1));  // patch rows (uniform)
-    const int SW = WAVE / PR;                            // patch columns (step width)
-    const int lc = L / PR, lr = L - lc * PR;
-    const bool lane_ok = lc < SW;
-    const int ncen = (nqc + SW - 1) / SW;  // steps over the tile's own columns
+    const int PR = 1 << lpr, lsw = 6 - lpr, SW = 1 << lsw;  // patch rows, step columns
+    const int lr = L & (PR - 1), lc = L >> lpr;
+    const int ncen = (nqc + SW - 1) >> lsw;  // steps over the tile's own columns
     for (int blk = lo; blk <= hi; blk += PR) {
         const int bhi = min(blk + PR - 1, hi);
         const int i = blk + lr;
@@ -455,7 +451,7 @@ __device__ __forceinline__ void scan_pruned(TileState<QR, QC>& S, const FrameDes
             const float ip = ipn;
             if (st + 1 < ns) ipn = rowp[min(max(step_col(st + 1) + lc, 0), W - 1)];
             const int j = jc + lc;
-            const bool jok = lane_ok && j >= 0 && j < W;
+            const bool jok = j >= 0 && j < W;
             const uint32_t idx = (uint32_t)i * (uint32_t)W + (uint32_t)j;
             float b[QC];
 #pragma unroll

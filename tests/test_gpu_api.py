@@ -141,7 +141,7 @@ def test_failed_context_is_sticky():
         _lib.knnf_destroy(c)
 
 
-@pytest.mark.parametrize("chunk", [8, 16, 32, 64])
+@pytest.mark.parametrize("chunk", [8, 16, 32])
 def test_window_chunks_bit_exact(ctx, chunk):
     cases = [("brain", 33, 129, 16, 7, 0.01), ("unif", 25, 90, 12, 4, 1.0),
              ("brain", 17, 130, 40, 14, 0.01), ("unif", 1, 70, 5, 0, 0.01),
@@ -169,7 +169,7 @@ def test_window_chunks_full_frame_equal(ctx):
     pc1, prob = spec.make()
     outs = []
     for plan in (dict(search=0), dict(search=1, chunk_rows=8), dict(search=1, chunk_rows=16),
-                 dict(search=1, chunk_rows=32), dict(search=1, chunk_rows=64)):
+                 dict(search=1, chunk_rows=32)):
         say(f"config1 plan {plan}")
         df = DeviceFrame(pc1, prob, spec.K, spec.R, spec.lam)
         _lib.knnf_filter(ctx, df.as_c(), dict(plan, flags=NOCHECK), current_stream())
