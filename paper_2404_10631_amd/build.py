@@ -25,7 +25,8 @@ ROOT = os.path.dirname(HERE)
 
 SOURCES = ["knnf_kernels.hip", "knnf_pc1.hip", "knnf_svm.hip", "knnf_api.cpp", "knnf_server.cpp"]
 
-HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+HIPCC = os.environ.get("HIPCC", os.path.join(ROCM, "bin", "hipcc"))
 ARCH = os.environ.get("KNNF_OFFLOAD_ARCH", "gfx950")
 
 COMMON_FLAGS = [
@@ -63,7 +64,9 @@ def build(verbose: bool = False, extra: list[str] | None = None) -> str:
         for r in list(ex.map(lambda c: subprocess.run(c, check=True), cmds)):
             pass
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    # roctx: the serving stages' trace ranges
+    cmd = ([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+           + ["-L", os.path.join(ROCM, "lib"), "-lrocprofiler-sdk-roctx"])
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

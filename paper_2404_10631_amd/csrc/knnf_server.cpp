@@ -16,12 +16,23 @@
 //   3. watches step completion events and marks a frame done when the last
 //      step holding its tiles has finished.
 // In plain mode each step is one whole frame, launched alone (the baseline).
+//
+// Tracing: every frame carries one roctx range per serving stage, named
+// "knnf frame <ticket> <H>x<W> <stage>" with the stages "queued" (submitted,
+// waiting for pool memory), "ready" (admitted: inputs copying, waiting for a
+// step) and "on gpu" (first tile launched until its last step completes);
+// the host calls that enqueue input copies and launch steps are pushed as
+// "knnf h2d enqueue" and "knnf step" ranges on the calling thread.
+// rocprofv3 --marker-trace records them; without a tool attached they cost
+// a call into an empty dispatch table.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
 #include <deque>
 #include <map>
 #include <mutex>
@@ -96,7 +107,21 @@ struct Job {
     const void* map_pc1 = nullptr;   // device views of small pinned inputs (else null)
     const void* map_prob = nullptr;
     double t_arrival = 0, t_admit = 0, t_launch = -1, t_done = 0;
+    roctx_range_id_t span = 0;  // roctx range of the current serving stage
+    bool span_open = false;
 };
+
+// Ends the frame's current stage range and, if `stage` is given, opens the next.
+void stage(Job& j, const char* stage) {
+    if (j.span_open) roctxRangeStop(j.span);
+    j.span_open = false;
+    if (!stage) return;
+    char name[96];
+    std::snprintf(name, sizeof name, "knnf frame %llu %dx%d %s", (unsigned long long)j.ticket,
+                  j.hf.H, j.hf.W, stage);
+    j.span = roctxRangeStartA(name);
+    j.span_open = true;
+}
 
 struct Step {
     hipEvent_t done = nullptr;
@@ -220,9 +245,11 @@ bool copy_stream_idle(knnf_server* s) {
 hipError_t enqueue_copies(knnf_server* s, void* d1, const void* h1, size_t n1, void* d2,
                           const void* h2, size_t n2, hipEvent_t ev) {
     hipError_t e = ev ? hipSuccess : hipErrorOutOfMemory;
+    roctxRangePushA("knnf h2d enqueue");
     if (e == hipSuccess) e = hipMemcpyAsync(d1, h1, n1, hipMemcpyHostToDevice, s->copy_stream);
     if (e == hipSuccess) e = hipMemcpyAsync(d2, h2, n2, hipMemcpyHostToDevice, s->copy_stream);
     if (e == hipSuccess) e = hipEventRecord(ev, s->copy_stream);
+    roctxRangePop();
     return e;
 }
 
@@ -250,6 +277,7 @@ void admit(knnf_server* s) {
             }
             j.state = ADMITTED;
             j.t_admit = now_s();
+            stage(j, "ready");
             s->ready.push_back(j.ticket);
         } else {
             j.state = COPYING;
@@ -283,10 +311,12 @@ void copier(knnf_server* s) {
         lk.unlock();
         hipError_t e;
         if (ev && m1 && m2 && !copy_stream_idle(s)) {
+            roctxRangePushA("knnf h2d enqueue");
             e = (hipError_t)knnf::launch_copy_pair((const uint32_t*)m1, (uint32_t*)d1,
                                                    (uint32_t)(n1 / 4), (const uint32_t*)m2,
                                                    (uint32_t*)d2, (uint32_t)(n2 / 4), s->copy_stream);
             if (e == hipSuccess) e = hipEventRecord(ev, s->copy_stream);
+            roctxRangePop();
         } else {
             e = enqueue_copies(s, d1, h1, n1, d2, h2, n2, ev);
         }
@@ -302,6 +332,7 @@ void copier(knnf_server* s) {
         j.copied = ev;
         j.state = ADMITTED;
         j.t_admit = now_s();
+        stage(j, "ready");
         s->ready.push_back(tk);
         s->cv.notify_one();
     }
@@ -310,6 +341,7 @@ void copier(knnf_server* s) {
 void finish_job(knnf_server* s, Job& j, double t) {
     j.state = DONE;
     j.t_done = t;
+    stage(j, nullptr);
     if (j.copied) {
         s->event_pool.push_back(j.copied);
         j.copied = nullptr;
@@ -373,13 +405,17 @@ bool launch_step(knnf_server* s) {
         items.push_back(w);
         j.next_tile += take;
         ++j.outstanding;
-        if (j.t_launch < 0) j.t_launch = now_s();
+        if (j.t_launch < 0) {
+            j.t_launch = now_s();
+            stage(j, "on gpu");
+        }
         st->tickets.push_back(j.ticket);
         budget -= take;
         if (j.next_tile == j.ntiles) s->ready.pop_front();
         if (plain) break;
     }
     knnf_status rc;
+    roctxRangePushA("knnf step");
     if (plain || (items.size() == 1 && items[0].tile0 == 0 &&
                   items[0].ntiles == s->jobs[st->tickets[0]].ntiles)) {
         // one whole frame: the single-frame launch (no work table to copy)
@@ -387,6 +423,7 @@ bool launch_step(knnf_server* s) {
     } else {
         rc = knnf::launch_items(s->ctx, items.data(), (int)items.size(), s->plan, st->stream);
     }
+    roctxRangePop();
     if (rc == KNNF_EDEVICE || hipEventRecord(st->done, st->stream) != hipSuccess)
         server_fail(s, "server: step launch");
     else if (rc != KNNF_OK)
@@ -541,7 +578,8 @@ knnf_status knnf_server_submit(knnf_server* s, const knnf_host_frame* f, uint64_
     j.t_arrival = f->t_arrival >= 0 ? f->t_arrival : now_s();
     j.map_pc1 = m1;
     j.map_prob = m2;
-    s->jobs[j.ticket] = j;
+    Job& stored = s->jobs[j.ticket] = j;
+    stage(stored, "queued");
     s->queue.push_back(j.ticket);
     ++s->unfinished;
     *ticket = j.ticket;
@@ -631,8 +669,10 @@ knnf_status knnf_server_destroy(knnf_server* s) {
         hipStreamSynchronize(s->copy_stream);
         hipStreamDestroy(s->copy_stream);
     }
-    for (auto& kv : s->jobs)
+    for (auto& kv : s->jobs) {
         if (kv.second.copied) hipEventDestroy(kv.second.copied);
+        stage(kv.second, nullptr);  // frames never finished
+    }
     for (hipEvent_t e : s->event_pool) hipEventDestroy(e);
     hipSetDevice(prev);
     delete s;

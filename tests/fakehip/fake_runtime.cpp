@@ -7,6 +7,7 @@
 // completes.  "Device" memory is ordinary host memory, and pinned host
 // memory is reported as device-mapped (its device address is itself).
 #include "hip/hip_runtime.h"
+#include "rocprofiler-sdk-roctx/roctx.h"
 
 #include <atomic>
 #include <chrono>
@@ -17,7 +18,9 @@
 #include <map>
 #include <mutex>
 #include <set>
+#include <string>
 #include <thread>
+#include <vector>
 
 struct FakeEvent {
     std::mutex mu;
@@ -291,3 +294,54 @@ hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b) {
     *ms = (float)((tb - ta) * 1e3);
     return hipSuccess;
 }
+
+// ---- roctx: ranges are counted, and every started name is kept
+namespace {
+std::mutex g_tx_mu;
+std::set<roctx_range_id_t> g_tx_open;
+std::vector<std::string> g_tx_names;
+roctx_range_id_t g_tx_next = 1;
+long g_tx_started = 0, g_tx_bad_stops = 0;
+std::atomic<long> g_tx_pushed{0};
+thread_local int g_tx_depth = 0;
+}  // namespace
+
+extern "C" {
+void roctxMarkA(const char*) {}
+int roctxRangePushA(const char*) {
+    g_tx_pushed.fetch_add(1);
+    return g_tx_depth++;
+}
+int roctxRangePop(void) { return g_tx_depth > 0 ? --g_tx_depth : -1; }
+roctx_range_id_t roctxRangeStartA(const char* message) {
+    std::lock_guard<std::mutex> lk(g_tx_mu);
+    const roctx_range_id_t id = g_tx_next++;
+    g_tx_open.insert(id);
+    g_tx_names.emplace_back(message);
+    ++g_tx_started;
+    return id;
+}
+void roctxRangeStop(roctx_range_id_t id) {
+    std::lock_guard<std::mutex> lk(g_tx_mu);
+    if (g_tx_open.erase(id) == 0) ++g_tx_bad_stops;
+}
+}  // extern "C"
+
+namespace fakehip {
+long roctx_started() {
+    std::lock_guard<std::mutex> lk(g_tx_mu);
+    return g_tx_started;
+}
+long roctx_open() {
+    std::lock_guard<std::mutex> lk(g_tx_mu);
+    return g_tx_bad_stops ? -g_tx_bad_stops : (long)g_tx_open.size();
+}
+long roctx_pushed() { return g_tx_pushed.load(); }
+int roctx_depth() { return g_tx_depth; }
+bool roctx_saw(const char* substring) {
+    std::lock_guard<std::mutex> lk(g_tx_mu);
+    for (const std::string& n : g_tx_names)
+        if (n.find(substring) != std::string::npos) return true;
+    return false;
+}
+}  // namespace fakehip

@@ -7,6 +7,7 @@
 // Each test prints "ok <name>" or "FAIL <name>: ..." and the program exits
 // non-zero if any failed.  Usage: test_server_fake [name ...]
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <atomic>
 #include <chrono>
@@ -201,6 +202,43 @@ bool test_mixed_stream_equals_alone() {
     }
     CHECK((uint64_t)(fakedev::tiles_run.load() - t0) == tiles);
     CHECK(knnf_server_destroy(s) == KNNF_OK);
+    return true;
+}
+
+// Every frame passes through the three stage ranges (queued, ready, on gpu),
+// each range opened is closed by the time its frame is done, and the
+// thread-local push/pop ranges of the copy and launch calls are balanced.
+bool test_trace_ranges() {
+    Env env(16 << 20);
+    knnf_server* s = nullptr;
+    const knnf_server_opts o = opts(KNNF_SERVE_BATCHED, 64);
+    const long open0 = fakehip::roctx_open(), started0 = fakehip::roctx_started();
+    const long pushed0 = fakehip::roctx_pushed();
+    CHECK(open0 == 0);
+    CHECK(knnf_server_create(&s, env.ctx, env.pool, env.pool_bytes, &o) == KNNF_OK);
+    auto frames = mixed_frames(12, 5, false);
+    std::vector<uint64_t> tk;
+    for (auto& f : frames) {
+        uint64_t t = 0;
+        const knnf_host_frame h = f->host();
+        CHECK(knnf_server_submit(s, &h, &t) == KNNF_OK);
+        tk.push_back(t);
+    }
+    CHECK(knnf_server_drain(s, 60.0) == KNNF_OK);
+    CHECK(fakehip::roctx_open() == 0);  // every frame done: no stage left open
+    CHECK(fakehip::roctx_started() - started0 == 3 * (long)frames.size());
+    CHECK(fakehip::roctx_pushed() - pushed0 >= 2);  // copies and steps
+    const std::string last = "knnf frame " + std::to_string(tk.back()) + " ";
+    CHECK(fakehip::roctx_saw((last + std::to_string(frames.back()->H) + "x" +
+                              std::to_string(frames.back()->W) + " on gpu").c_str()));
+    CHECK(fakehip::roctx_saw("queued") && fakehip::roctx_saw("ready"));
+    for (uint64_t t : tk) CHECK(knnf_server_release(s, t) == KNNF_OK);
+    // a frame still queued when the server is destroyed has its range closed
+    uint64_t t = 0;
+    const knnf_host_frame h = frames[0]->host();
+    CHECK(knnf_server_submit(s, &h, &t) == KNNF_OK);
+    CHECK(knnf_server_destroy(s) == KNNF_OK);
+    CHECK(fakehip::roctx_open() == 0);
     return true;
 }
 
@@ -503,6 +541,7 @@ int main(int argc, char** argv) {
         {"non_finite_submit", test_non_finite_submit},
         {"concurrent_submitters", test_concurrent_submitters},
         {"filter_batch_tables", test_filter_batch_tables},
+        {"trace_ranges", test_trace_ranges},
         {"copy_failure_is_sticky", test_copy_failure_is_sticky},  // last: fails its context
     };
     for (const Test& t : tests) {

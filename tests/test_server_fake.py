@@ -56,7 +56,7 @@ def build_and_run(d, obj, name, flags, env=None):
     out = run.stdout + run.stderr
     assert run.returncode == 0, out[-4000:]
     assert "FAIL" not in run.stdout
-    assert run.stdout.count("\nok ") + run.stdout.startswith("ok ") == 10, run.stdout
+    assert run.stdout.count("\nok ") + run.stdout.startswith("ok ") == 11, run.stdout
     return out
 
 
