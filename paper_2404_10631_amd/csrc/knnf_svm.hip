@@ -19,12 +19,11 @@
 // else is per-pixel arithmetic, so the kernel is HBM-bound.  A block owns 256
 // consecutive pixels.  It stages the cube through LDS in chunks of 32 bands:
 // eight lanes cover one pixel's 128-byte piece of the chunk with 16-byte
-// loads, so every cache line that a load touches is used whole.  The
-// hyperplane weights of the chunk (M x 32 values) are staged beside it.
-// Then each lane owns one pixel for the dot products (the weights read as
-// LDS broadcasts: read straight from memory at wave-uniform addresses they
-// became scalar loads whose waits lay on every wave's critical path) and for
-// the coupling iteration, whose sweep count differs from pixel to pixel.
+// loads.  The hyperplane weights of the chunk (M x 32 values) are staged
+// beside it.  Then each lane owns one pixel for the dot products (the weights
+// read as LDS broadcasts: read straight from memory at wave-uniform addresses
+// they became scalar loads whose waits lay on every wave's critical path) and
+// for the coupling iteration, whose sweep count differs from pixel to pixel.
 // The loads of the next chunk are in flight while the current one is used.
 // The fused variant (PC1 = true) also accumulates the PC1 projection from the
 // same chunks, so the pipeline's two steps before the filter read the cube
@@ -52,8 +51,9 @@ __device__ __forceinline__ constexpr int pair_index(int i, int j) {
 }
 
 // Block-wide (min, max) of per-thread values -> pairs[2 * blockIdx.x ..].
+template <int NT>
 __device__ void svm_publish_minmax(double lo, double hi, double* pairs) {
-    __shared__ double slo[SVM_THREADS / 64], shi[SVM_THREADS / 64];
+    __shared__ double slo[NT / 64], shi[NT / 64];
     for (int m = 1; m < 64; m <<= 1) {
         lo = fmin(lo, __shfl_xor(lo, m));
         hi = fmax(hi, __shfl_xor(hi, m));
@@ -65,7 +65,7 @@ __device__ void svm_publish_minmax(double lo, double hi, double* pairs) {
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int k = 1; k < SVM_THREADS / 64; ++k) {
+        for (int k = 1; k < NT / 64; ++k) {
             lo = fmin(lo, slo[k]);
             hi = fmax(hi, shi[k]);
         }
@@ -74,61 +74,30 @@ __device__ void svm_publish_minmax(double lo, double hi, double* pairs) {
     }
 }
 
-// PC1 = true also accumulates the PC1 projection of each pixel (Sec. II.C.2:
-// the cube centred by the band averages, times the first eigenvector),
-// band by band in ascending order in binary64, from the same staged chunks:
-// the step before the filter reads the cube once for both of its outputs.
-template <int C, bool VEC, bool PC1>
-__global__ void __launch_bounds__(SVM_THREADS)
-svm_prob_kernel(const float* __restrict__ cube, int64_t npix, int bands,
-                const double* __restrict__ w, const double* __restrict__ bias,
-                const double* __restrict__ A, const double* __restrict__ B,
-                float* __restrict__ out, const double* __restrict__ mean,
-                const double* __restrict__ vec, float* __restrict__ band,
-                double* __restrict__ ws, double* __restrict__ pairs) {
-    constexpr int M = C * (C - 1) / 2;
-    __shared__ __attribute__((aligned(16))) float tile[SVM_THREADS * SVM_STRIDE];
-    // weights of one chunk: the M hyperplanes, then (PC1) averages and eigenvector
-    constexpr int NWT = (M + (PC1 ? 2 : 0)) * SVM_CHUNK;
-    constexpr int NW = (NWT + SVM_THREADS - 1) / SVM_THREADS;  // per thread
-    __shared__ __attribute__((aligned(16))) double wl[NWT];
-    const int tid = threadIdx.x;
-    const int64_t first = (int64_t)blockIdx.x * SVM_THREADS;
-    const int64_t last = npix - 1;
+// 1 / x in binary64 for the finite, normal x of the sigmoid and the coupling:
+// the hardware reciprocal refined by two Newton steps (an error of an ulp or
+// so, far below the 1e-6 the probabilities are held to, for a third of the
+// instructions of an IEEE division).
+__device__ __forceinline__ double rcp64(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
 
-    // (i) decision values, accumulated band by band in ascending order
-    double f[M];
-#pragma unroll
-    for (int m = 0; m < M; ++m) f[m] = 0.0;
-    double pj = 0.0;  // PC1 projection
-    const float* row = tile + tid * SVM_STRIDE;
-    // Staging of cube[first .. first+255][c0 .. c0+31] (rows past the frame
-    // repeat its last pixel, bands past the cube read as 0).  The next chunk
-    // is loaded into registers while the current one is used from LDS.
-    // 16-byte path: lane (q, r0) loads column 4q of rows r0, r0 + 32, ...
-    // Scalar path: lane (q, r0) loads band q of rows r0, r0 + 8, ...
-    constexpr int NLOAD = VEC ? 8 : 32;
-    using Piece = typename std::conditional<VEC, float4, float>::type;
-    Piece v[NLOAD];
+// Weights of the chunk of bands c0 .. c0+31 for thread tid of NT: the M
+// hyperplanes, then (PC1) the band averages and the eigenvector, as (m, k)
+// = (e / 32, e % 32) with e = tid + NT * i; bands past the cube read as 0.
+template <int NT, int M, bool PC1>
+struct ChunkWeights {
+    static constexpr int NWT = (M + (PC1 ? 2 : 0)) * SVM_CHUNK;
+    static constexpr int NW = (NWT + NT - 1) / NT;  // per thread
     double wv[NW];
-    const int q = VEC ? (tid & 7) : (tid & 31);
-    const int r0 = VEC ? (tid >> 3) : (tid >> 5);
-    constexpr int RSTEP = VEC ? 32 : 8;
-    auto fetch = [&](int c0) {
-        const int b = c0 + (VEC ? 4 * q : q);
-#pragma unroll
-        for (int i = 0; i < NLOAD; ++i) {
-            int64_t p = first + r0 + RSTEP * i;
-            p = p < npix ? p : last;
-            if constexpr (VEC)
-                v[i] = b < bands ? *(const float4*)(cube + p * (int64_t)bands + b)
-                                 : make_float4(0.f, 0.f, 0.f, 0.f);
-            else
-                v[i] = b < bands ? cube[p * (int64_t)bands + b] : 0.f;
-        }
+    __device__ __forceinline__ void fetch(int c0, int bands, const double* __restrict__ w,
+                                          const double* __restrict__ mean,
+                                          const double* __restrict__ vec) {
 #pragma unroll
         for (int i = 0; i < NW; ++i) {
-            const int e = tid + SVM_THREADS * i;   // (m, k) = (e / 32, e % 32)
+            const int e = (int)threadIdx.x + NT * i;
             const int m = e / SVM_CHUNK;
             const int bb = c0 + (e % SVM_CHUNK);
             double x = 0.0;
@@ -136,69 +105,61 @@ svm_prob_kernel(const float* __restrict__ cube, int64_t npix, int bands,
                 x = m < M ? w[(int64_t)m * bands + bb] : (m == M ? mean[bb] : vec[bb]);
             wv[i] = x;
         }
-    };
-    fetch(0);
-    for (int c0 = 0; c0 < bands; c0 += SVM_CHUNK) {
-#pragma unroll
-        for (int i = 0; i < NLOAD; ++i) {
-            if constexpr (VEC)
-                *(float4*)(tile + (r0 + RSTEP * i) * SVM_STRIDE + 4 * q) = v[i];
-            else
-                tile[(r0 + RSTEP * i) * SVM_STRIDE + q] = v[i];
-        }
+    }
+    __device__ __forceinline__ void stage(double* wl) const {
 #pragma unroll
         for (int i = 0; i < NW; ++i) {
-            const int e = tid + SVM_THREADS * i;
+            const int e = (int)threadIdx.x + NT * i;
             if (e < NWT) wl[e] = wv[i];
         }
-        __syncthreads();
-        if (c0 + SVM_CHUNK < bands) fetch(c0 + SVM_CHUNK);
-        if (c0 + SVM_CHUNK <= bands) {
-#pragma unroll
-            for (int k = 0; k < SVM_CHUNK / 4; ++k) {
-                const float4 x4 = *(const float4*)(row + 4 * k);
-                const double x[4] = {(double)x4.x, (double)x4.y, (double)x4.z, (double)x4.w};
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-#pragma unroll
-                    for (int m = 0; m < M; ++m)
-                        f[m] = fma(wl[m * SVM_CHUNK + 4 * k + e], x[e], f[m]);
-                    if constexpr (PC1)
-                        pj = fma(x[e] - wl[M * SVM_CHUNK + 4 * k + e],
-                                 wl[(M + 1) * SVM_CHUNK + 4 * k + e], pj);
-                }
-            }
-        } else {
-            const int nb = bands - c0;
-            for (int k = 0; k < nb; ++k) {
-                const double x = (double)row[k];
-#pragma unroll
-                for (int m = 0; m < M; ++m) f[m] = fma(wl[m * SVM_CHUNK + k], x, f[m]);
-                if constexpr (PC1)
-                    pj = fma(x - wl[M * SVM_CHUNK + k], wl[(M + 1) * SVM_CHUNK + k], pj);
-            }
-        }
-        __syncthreads();
     }
-    const int64_t pix = first + tid;
-    if constexpr (PC1) {
-        if (ws) {
-            // every thread of the block takes part (pixels past the frame add nothing)
-            const bool in = pix < npix;
-            svm_publish_minmax(in ? pj : __builtin_inf(), in ? pj : -__builtin_inf(), pairs);
-            if (in) ws[pix] = pj;
-        } else if (pix < npix) {
-            band[pix] = (float)pj;
-        }
-    }
-    if (pix >= npix) return;
+};
 
-    // (ii) binary probabilities; r[m] is that of the pair's first class
+// (i) for the bands c0 .. c0+nb-1 of one pixel, from its staged row (the
+// chunk's first band at row[0]) and the chunk's weights wl: the decision
+// values f and (PC1) the projection pj, band by band in ascending order.
+template <int M, bool PC1>
+__device__ __forceinline__ void svm_dot_chunk(const float* row, int nb, const double* wl,
+                                              double (&f)[M], double& pj) {
+    if (nb == SVM_CHUNK) {
+#pragma unroll
+        for (int k = 0; k < SVM_CHUNK / 4; ++k) {
+            const float4 x4 = *(const float4*)(row + 4 * k);
+            const double x[4] = {(double)x4.x, (double)x4.y, (double)x4.z, (double)x4.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+#pragma unroll
+                for (int m = 0; m < M; ++m) f[m] = fma(wl[m * SVM_CHUNK + 4 * k + e], x[e], f[m]);
+                if constexpr (PC1)
+                    pj = fma(x[e] - wl[M * SVM_CHUNK + 4 * k + e], wl[(M + 1) * SVM_CHUNK + 4 * k + e],
+                             pj);
+            }
+        }
+    } else {
+        for (int k = 0; k < nb; ++k) {
+            const double x = (double)row[k];
+#pragma unroll
+            for (int m = 0; m < M; ++m) f[m] = fma(wl[m * SVM_CHUNK + k], x, f[m]);
+            if constexpr (PC1) pj = fma(x - wl[M * SVM_CHUNK + k], wl[(M + 1) * SVM_CHUNK + k], pj);
+        }
+    }
+}
+
+// Steps (ii) and (iii) for one pixel: sigmoids of the decision values f,
+// then the coupling sweeps; writes the C probabilities to o.
+template <int C>
+__device__ __forceinline__ void svm_couple(const double (&f)[C * (C - 1) / 2],
+                                           const double* __restrict__ bias,
+                                           const double* __restrict__ A,
+                                           const double* __restrict__ B, float* o) {
+    constexpr int M = C * (C - 1) / 2;
+    // (ii) binary probabilities; r[m] is that of the pair's first class (z is
+    // capped where the clamp decides anyway, so 1 + exp(z) stays finite)
     double r[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
-        const double z = (f[m] + bias[m]) * A[m] + B[m];
-        const double s = 1.0 / (1.0 + exp(z));
+        const double z = fmin((f[m] + bias[m]) * A[m] + B[m], 700.0);
+        const double s = rcp64(1.0 + exp(z));
         r[m] = fmin(fmax(s, SVM_CLAMP), 1.0 - SVM_CLAMP);
     }
     // (iii) coupling.  Q[t][t] sums r_st^2 over s in ascending order;
@@ -232,7 +193,7 @@ svm_prob_kernel(const float* __restrict__ cube, int64_t npix, int bands,
 #pragma unroll
     for (int t = 0; t < C; ++t) {
         p[t] = 1.0 / C;
-        rq[t] = 1.0 / qtt[t];
+        rq[t] = rcp64(qtt[t]);
     }
     double pqp = 0.0;
 #pragma unroll
@@ -252,7 +213,7 @@ svm_prob_kernel(const float* __restrict__ cube, int64_t npix, int bands,
 #pragma unroll
         for (int t = 0; t < C; ++t) {
             const double d = (pqp - qp[t]) * rq[t];
-            const double inv = 1.0 / (1.0 + d);
+            const double inv = rcp64(1.0 + d);
             pqp = fma(d, fma(d, qtt[t], 2.0 * qp[t]), pqp) * inv * inv;
 #pragma unroll
             for (int j = 0; j < C; ++j) qp[j] = fma(d, Q(j, t), qp[j]) * inv;
@@ -261,9 +222,101 @@ svm_prob_kernel(const float* __restrict__ cube, int64_t npix, int bands,
             for (int j = 0; j < C; ++j) p[j] *= inv;
         }
     }
-    float* o = out + pix * C;
 #pragma unroll
     for (int t = 0; t < C; ++t) o[t] = (float)p[t];
+}
+
+// A pixel's outputs once its decision values f and projection pj are
+// complete (every thread of the block calls it).
+template <int C, int NT, bool PC1>
+__device__ __forceinline__ void svm_finish(int64_t pix, int64_t npix,
+                                           const double (&f)[C * (C - 1) / 2], double pj,
+                                           const double* __restrict__ bias,
+                                           const double* __restrict__ A,
+                                           const double* __restrict__ B, float* __restrict__ out,
+                                           float* __restrict__ band, double* __restrict__ ws,
+                                           double* __restrict__ pairs) {
+    const bool in = pix < npix;
+    if constexpr (PC1) {
+        if (ws) {
+            // every thread of the block takes part (pixels past the frame add nothing)
+            svm_publish_minmax<NT>(in ? pj : __builtin_inf(), in ? pj : -__builtin_inf(), pairs);
+            if (in) ws[pix] = pj;
+        } else if (in) {
+            band[pix] = (float)pj;
+        }
+    }
+    if (in) svm_couple<C>(f, bias, A, B, out + pix * C);
+}
+
+// PC1 = true also accumulates the PC1 projection of each
+// pixel (Sec. II.C.2: the cube centred by the band averages, times the first
+// eigenvector), band by band in ascending order in binary64, from the same
+// staged chunks: the step before the filter reads the cube once for both of
+// its outputs.
+template <int C, bool VEC, bool PC1>
+__global__ void __launch_bounds__(SVM_THREADS)
+svm_prob_kernel(const float* __restrict__ cube, int64_t npix, int bands,
+                const double* __restrict__ w, const double* __restrict__ bias,
+                const double* __restrict__ A, const double* __restrict__ B,
+                float* __restrict__ out, const double* __restrict__ mean,
+                const double* __restrict__ vec, float* __restrict__ band,
+                double* __restrict__ ws, double* __restrict__ pairs) {
+    constexpr int M = C * (C - 1) / 2;
+    using Weights = ChunkWeights<SVM_THREADS, M, PC1>;
+    __shared__ __attribute__((aligned(16))) float tile[SVM_THREADS * SVM_STRIDE];
+    __shared__ __attribute__((aligned(16))) double wl[Weights::NWT];
+    const int tid = threadIdx.x;
+    const int64_t first = (int64_t)blockIdx.x * SVM_THREADS;
+    const int64_t last = npix - 1;
+
+    double f[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) f[m] = 0.0;
+    double pj = 0.0;  // PC1 projection
+    const float* row = tile + tid * SVM_STRIDE;
+    // Staging of cube[first .. first+255][c0 .. c0+31] (rows past the frame
+    // repeat its last pixel, bands past the cube read as 0).  The next chunk
+    // is loaded into registers while the current one is used from LDS.
+    // 16-byte path: lane (q, r0) loads column 4q of rows r0, r0 + 32, ...
+    // Scalar path: lane (q, r0) loads band q of rows r0, r0 + 8, ...
+    constexpr int NLOAD = VEC ? 8 : 32;
+    using Piece = typename std::conditional<VEC, float4, float>::type;
+    Piece v[NLOAD];
+    Weights wt;
+    const int q = VEC ? (tid & 7) : (tid & 31);
+    const int r0 = VEC ? (tid >> 3) : (tid >> 5);
+    constexpr int RSTEP = VEC ? 32 : 8;
+    auto fetch = [&](int c0) {
+        const int b = c0 + (VEC ? 4 * q : q);
+#pragma unroll
+        for (int i = 0; i < NLOAD; ++i) {
+            int64_t p = first + r0 + RSTEP * i;
+            p = p < npix ? p : last;
+            if constexpr (VEC)
+                v[i] = b < bands ? *(const float4*)(cube + p * (int64_t)bands + b)
+                                 : make_float4(0.f, 0.f, 0.f, 0.f);
+            else
+                v[i] = b < bands ? cube[p * (int64_t)bands + b] : 0.f;
+        }
+        wt.fetch(c0, bands, w, mean, vec);
+    };
+    fetch(0);
+    for (int c0 = 0; c0 < bands; c0 += SVM_CHUNK) {
+#pragma unroll
+        for (int i = 0; i < NLOAD; ++i) {
+            if constexpr (VEC)
+                *(float4*)(tile + (r0 + RSTEP * i) * SVM_STRIDE + 4 * q) = v[i];
+            else
+                tile[(r0 + RSTEP * i) * SVM_STRIDE + q] = v[i];
+        }
+        wt.stage(wl);
+        __syncthreads();
+        if (c0 + SVM_CHUNK < bands) fetch(c0 + SVM_CHUNK);
+        svm_dot_chunk<M, PC1>(row, min(SVM_CHUNK, bands - c0), wl, f, pj);
+        __syncthreads();
+    }
+    svm_finish<C, SVM_THREADS, PC1>(first + tid, npix, f, pj, bias, A, B, out, band, ws, pairs);
 }
 
 struct SvmArgs {
@@ -276,30 +329,32 @@ struct SvmArgs {
 };
 
 template <int C, bool PC1>
-int launch_c(const SvmArgs& a, void* stream) {
+int launch_c(const SvmArgs& a, void* stream, int* nblocks) {
+    const hipStream_t st = (hipStream_t)stream;
     const int64_t blocks = (a.npix + SVM_THREADS - 1) / SVM_THREADS;
     const bool vec = a.bands % 4 == 0 && ((uintptr_t)a.cube & 15) == 0;
     if (vec)
         hipLaunchKernelGGL((svm_prob_kernel<C, true, PC1>), dim3((uint32_t)blocks), dim3(SVM_THREADS),
-                           0, (hipStream_t)stream, a.cube, a.npix, a.bands, a.w, a.bias, a.A, a.B,
-                           a.out, a.mean, a.vec, a.band, a.ws, a.pairs);
+                           0, st, a.cube, a.npix, a.bands, a.w, a.bias, a.A, a.B, a.out, a.mean,
+                           a.vec, a.band, a.ws, a.pairs);
     else
         hipLaunchKernelGGL((svm_prob_kernel<C, false, PC1>), dim3((uint32_t)blocks), dim3(SVM_THREADS),
-                           0, (hipStream_t)stream, a.cube, a.npix, a.bands, a.w, a.bias, a.A, a.B,
-                           a.out, a.mean, a.vec, a.band, a.ws, a.pairs);
+                           0, st, a.cube, a.npix, a.bands, a.w, a.bias, a.A, a.B, a.out, a.mean,
+                           a.vec, a.band, a.ws, a.pairs);
+    if (nblocks) *nblocks = (int)blocks;
     return (int)hipGetLastError();
 }
 
 template <bool PC1>
-int launch_classes(int classes, const SvmArgs& a, void* stream) {
+int launch_classes(int classes, const SvmArgs& a, void* stream, int* nblocks) {
     switch (classes) {
-        case 2: return launch_c<2, PC1>(a, stream);
-        case 3: return launch_c<3, PC1>(a, stream);
-        case 4: return launch_c<4, PC1>(a, stream);
-        case 5: return launch_c<5, PC1>(a, stream);
-        case 6: return launch_c<6, PC1>(a, stream);
-        case 7: return launch_c<7, PC1>(a, stream);
-        case 8: return launch_c<8, PC1>(a, stream);
+        case 2: return launch_c<2, PC1>(a, stream, nblocks);
+        case 3: return launch_c<3, PC1>(a, stream, nblocks);
+        case 4: return launch_c<4, PC1>(a, stream, nblocks);
+        case 5: return launch_c<5, PC1>(a, stream, nblocks);
+        case 6: return launch_c<6, PC1>(a, stream, nblocks);
+        case 7: return launch_c<7, PC1>(a, stream, nblocks);
+        case 8: return launch_c<8, PC1>(a, stream, nblocks);
         default: return (int)hipErrorInvalidValue;
     }
 }
@@ -309,7 +364,7 @@ int launch_classes(int classes, const SvmArgs& a, void* stream) {
 int launch_svm(const float* cube, int64_t npix, int bands, int classes, const double* w,
                const double* bias, const double* A, const double* B, float* out, void* stream) {
     const SvmArgs a{cube, npix, bands, w, bias, A, B, nullptr, nullptr, out, nullptr, nullptr, nullptr};
-    return launch_classes<false>(classes, a, stream);
+    return launch_classes<false>(classes, a, stream, nullptr);
 }
 
 int svm_pixels_per_block() { return SVM_THREADS; }
@@ -318,9 +373,8 @@ int launch_svm_pc1(const float* cube, int64_t npix, int bands, int classes, cons
                    const double* bias, const double* A, const double* B, const double* mean,
                    const double* vec, float* out, float* band, double* ws, double* pairs,
                    int* nblocks, void* stream) {
-    *nblocks = (int)((npix + SVM_THREADS - 1) / SVM_THREADS);
     const SvmArgs a{cube, npix, bands, w, bias, A, B, mean, vec, out, band, ws, pairs};
-    return launch_classes<true>(classes, a, stream);
+    return launch_classes<true>(classes, a, stream, nblocks);
 }
 
 }  // namespace knnf

@@ -76,6 +76,13 @@ CASES = [
     ("C8", 19, 23, 96, 8, "brain"),
     ("one-pixel", 1, 1, 128, 4, "brain"),
     ("ragged-block", 1, 257, 128, 4, "brain"),
+    ("bands-4", 13, 11, 4, 4, "derma"),
+    ("bands-12-C2", 7, 300, 12, 2, "brain"),
+    ("bands-100-C8", 11, 29, 100, 8, "derma"),
+    ("bands-124-C5", 9, 31, 124, 5, "brain"),
+    ("bands-124-C2", 5, 40, 124, 2, "brain"),
+    ("one-pixel-100", 1, 1, 100, 4, "derma"),
+    ("ragged-129-100", 1, 129, 100, 4, "derma"),
 ]
 
 

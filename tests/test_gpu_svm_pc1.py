@@ -95,6 +95,9 @@ CASES = [
     ("C8", 19, 23, 96, 8, "brain"),
     ("one-pixel", 1, 1, 128, 4, "brain"),
     ("ragged-block", 1, 257, 128, 4, "brain"),
+    ("bands-100-C8", 11, 29, 100, 8, "derma"),
+    ("ragged-129-100", 1, 129, 100, 4, "derma"),
+    ("bands-4", 13, 11, 4, 4, "derma"),
 ]
 
 
