@@ -2,10 +2,16 @@
 benchmark times: the 64 uneven brain-like frames and the 1024 dermatology-like
 50 x 50 frames in one batched launch, and the mixed S/M/L serving stream
 through the batching server.  The 1024 small frames are checked at every
-pixel; the uneven and served frames at sampled positions (the oracle computes
-them one by one); neighbour indices, distances and classes bit-exact,
-probabilities within 1e-6.
+pixel against the oracle run here.  The uneven and served frames are checked
+at sampled positions against the oracle run here (neighbour indices,
+distances and classes bit-exact, probabilities within 1e-6) and at every
+pixel against digests of the oracle's whole-frame outputs that
+tests/golden/oracle_digests.py wrote (the oracle needs about half an hour of
+CPU for them): indices, distance bits, classes and probability bits equal.
 """
+import importlib.util
+import json
+import os
 import sys
 
 import numpy as np
@@ -48,6 +54,33 @@ def sample_pixels(H, W, n, rng):
     return np.unique(pix)
 
 
+_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _digest_module():
+    spec = importlib.util.spec_from_file_location("oracle_digests",
+                                                  os.path.join(_GOLDEN, "oracle_digests.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def oracle_digests(name):
+    with open(os.path.join(_GOLDEN, "oracle_digests.json")) as f:
+        return json.load(f)[name]
+
+
+def check_digests(label, spec, data, outs, want):
+    """Every pixel of the device's outputs against the oracle's digests."""
+    dig = _digest_module()
+    got = dig.frame_record(spec, outs, data)
+    for key in ("gen", "H", "W", "seed", "K", "R"):
+        assert got[key] == want[key], f"{label}: digest file is for another frame ({key})"
+    assert got["inputs"] == want["inputs"], f"{label}: the input generator changed"
+    for key in ("nbr", "dist", "class", "prob"):
+        assert got[key] == want[key], f"{label}: {key} differs from the oracle's whole frame"
+
+
 def check_sampled(label, spec, data, outs, pix):
     go, gc, gn, gd = outs
     pc1, prob = data
@@ -77,10 +110,14 @@ def test_config2_uneven_batch_full_size(ctx, plan):
     _lib.knnf_filter_batch(ctx, [f.as_c() for f in frames], plan, current_stream())
     torch.cuda.synchronize()
     rng = np.random.default_rng(7)
+    want = oracle_digests("config2")
+    assert len(want) == len(wl.frames)
     for k, (s, d, f) in enumerate(zip(wl.frames, data, frames)):
-        check_sampled(f"config2 frame {k} ({s.H}x{s.W})", s, d, f.results(),
+        outs = f.results()
+        check_sampled(f"config2 frame {k} ({s.H}x{s.W})", s, d, outs,
                       sample_pixels(s.H, s.W, 120, rng))
-    say("config2: sampled pixels bit-exact")
+        check_digests(f"config2 frame {k} ({s.H}x{s.W})", s, d, outs, want[k])
+    say("config2: sampled pixels bit-exact, every pixel equal to the oracle's digests")
 
 
 def test_config3_small_frame_batch_full_size(ctx):
@@ -132,9 +169,12 @@ def test_config4_served_mix_full_size(ctx):
         replay(srv, hosts, arrivals, keep=lambda k, v: results.__setitem__(k, srv.view_arrays(v)),
                with_nbr=True)
     rng = np.random.default_rng(9)
+    want = oracle_digests("config4")
+    assert len(want) == len(specs)
     for k, (s, d) in enumerate(zip(specs, data)):
         go, gc, gn, gd = results[k]
         assert gn is not None and gd is not None
         check_sampled(f"config4 frame {k} ({s.H}x{s.W})", s, d, (go, gc, gn, gd),
                       sample_pixels(s.H, s.W, 64, rng))
-    say("config4: sampled pixels bit-exact")
+        check_digests(f"config4 frame {k} ({s.H}x{s.W})", s, d, (go, gc, gn, gd), want[k])
+    say("config4: sampled pixels bit-exact, every pixel equal to the oracle's digests")
