@@ -113,7 +113,14 @@ typedef struct knnf_ctx knnf_ctx;
  *                           is non-negative and binary32 rounding is monotone,
  *                           the skipped candidates could never be selected:
  *                           the outputs are bit-identical to the exhaustive
- *                           search.
+ *                           search.  With lambda = 0 (the spectral distance
+ *                           alone) a single-frame call (knnf_filter) under
+ *                           this search runs a 1-D selection instead when the
+ *                           band of 2R + 1 rows (clipped to H) holds at most
+ *                           16,384 pixels: each query row's band is sorted by
+ *                           PC1 value and each query walks outward from its
+ *                           own value; same outputs again.  Its launches
+ *                           leave the work counters (knnf_stats_*) unchanged.
  */
 typedef enum { KNNF_SEARCH_EXHAUSTIVE = 0, KNNF_SEARCH_PRUNED = 1 } knnf_search;
 

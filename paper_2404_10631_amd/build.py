@@ -23,7 +23,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libknnf.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["knnf_kernels.hip", "knnf_pc1.hip", "knnf_svm.hip", "knnf_api.cpp", "knnf_server.cpp"]
+SOURCES = ["knnf_kernels.hip", "knnf_spectral.hip", "knnf_pc1.hip", "knnf_svm.hip", "knnf_api.cpp",
+           "knnf_server.cpp"]
 
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.environ.get("HIPCC", os.path.join(ROCM, "bin", "hipcc"))

@@ -665,7 +665,10 @@ knnf_status knnf_filter(knnf_ctx* ctx, const knnf_frame* frame, const knnf_plan*
         if (st != KNNF_OK) return st;
     }
     desc.stats = ctx->stats_on ? ctx->d_stats : nullptr;
-    const int e = knnf::launch_filter_frame(desc, to_cfg(p), stream);
+    // lambda = 0 under the pruned search: the 1-D selection (work counters not kept)
+    const int e = p.search == KNNF_SEARCH_PRUNED && knnf::spectral_fits(desc)
+                      ? knnf::launch_spectral_frame(desc, stream)
+                      : knnf::launch_filter_frame(desc, to_cfg(p), stream);
     if (e != 0) return ctx_fail(ctx, (hipError_t)e, "knnf_filter launch");
     return KNNF_OK;
 }

@@ -1,0 +1,166 @@
+"""GPU parity of the lambda = 0 path (the 1-D selection in each query row's
+band sorted by PC1 value, used under the pruned search) against the oracle and
+against the exhaustive scan, through the C-ABI.
+
+Bar as everywhere: neighbour indices, distance bits and classes bit-exact,
+probabilities within 1e-6.  The cases aim at what the selection does
+differently from the scans: the binary searches (queries at both ends of the
+band, values repeated many times), runs of equal distance (one value on each
+side, several values that round to the same distance), bands at and just past
+the LDS capacity (16,384 pixels; past it the general kernel runs), one-row
+and one-column frames, K equal to the smallest band.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_10631_amd import _lib, inputs
+from paper_2404_10631_amd.frames import DeviceFrame, current_stream
+
+pytestmark = pytest.mark.gpu
+
+PROB_TOL = 1e-6
+PRUNED = dict(search=1, tile_rows=1, tile_cols=8, waves=1)
+EXHAUSTIVE = dict(search=0, tile_rows=2, tile_cols=8, waves=2)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    assert torch.cuda.is_available(), "no GPU visible"
+    c = _lib.knnf_create(0)
+    yield c
+    _lib.knnf_destroy(c)
+
+
+def run_gpu(ctx, pc1, prob, K, R, plan):
+    import torch
+
+    df = DeviceFrame(pc1, prob, K, R, 0.0, with_nbr=True)
+    df.clear_outputs()
+    _lib.knnf_filter(ctx, df.as_c(), plan, current_stream())
+    torch.cuda.synchronize()
+    return df.results()
+
+
+def check(ctx, label, pc1, prob, K, R, ref=None):
+    pc1 = np.ascontiguousarray(pc1, np.float32)
+    prob = np.ascontiguousarray(prob, np.float32)
+    if ref is None:
+        ref = oracle.knn_filter(pc1, prob, K, R, 0.0)
+    ro, rc, rn, rd = ref
+    outs = {}
+    for name, plan in (("pruned", PRUNED), ("exhaustive", EXHAUSTIVE)):
+        say(f"{label} {pc1.shape} K={K} R={R} {name}")
+        go, gc, gn, gd = run_gpu(ctx, pc1, prob, K, R, plan)
+        bad = np.argwhere(np.any(gn != rn, axis=-1))
+        assert bad.size == 0, f"{label} {name}: nbr differs at {bad[:5].tolist()} (of {len(bad)})"
+        assert np.array_equal(gd.view(np.uint32), rd.view(np.uint32)), f"{label} {name}: dist"
+        assert np.array_equal(gc, rc), f"{label} {name}: class"
+        err = float(np.max(np.abs(go.astype(np.float64) - ro.astype(np.float64))))
+        assert err <= PROB_TOL, f"{label} {name}: prob err {err}"
+        outs[name] = (go, gc, gn, gd)
+    for a, b in zip(outs["pruned"], outs["exhaustive"]):
+        assert np.array_equal(a.view(np.uint32) if a.dtype == np.float32 else a,
+                              b.view(np.uint32) if b.dtype == np.float32 else b), \
+            f"{label}: the two searches differ"
+
+
+def test_full_size_brain_frame(ctx):
+    """W 480 x H 380, K = 40, +-14 rows (a band of 13,920 pixels), every pixel."""
+    spec = inputs.config1().frames[0]
+    pc1, prob = spec.make()
+    check(ctx, "brain 380x480", pc1, prob, 40, 14)
+
+
+@pytest.mark.parametrize("H,W,K,R", [(50, 64, 8, 4), (17, 333, 40, 3), (64, 40, 64, 7)])
+def test_uniform_bands(ctx, H, W, K, R):
+    pc1, prob = inputs.g_unif(H, W, 3 + H)
+    check(ctx, "uniform", pc1, prob, K, R)
+
+
+def test_repeated_values(ctx):
+    """Eight distinct values over the frame: every run of equal distance holds
+    many pixels, on one side or both (a query halfway between two values)."""
+    rng = np.random.default_rng(31)
+    H, W, K, R = 40, 90, 40, 5
+    pc1 = (rng.integers(0, 8, size=(H, W)) / 8.0).astype(np.float32)
+    pc1[5, 7] = 0.0625  # exactly halfway between 0 and 0.125
+    _, prob = inputs.g_unif(H, W, 4)
+    check(ctx, "repeated", pc1, prob, K, R)
+
+
+def test_constant_frame(ctx):
+    """One value everywhere: the neighbours are the K lowest indices of the band."""
+    H, W, K, R = 30, 70, 17, 4
+    pc1 = np.full((H, W), 0.25, np.float32)
+    _, prob = inputs.g_unif(H, W, 5)
+    check(ctx, "constant", pc1, prob, K, R)
+
+
+def test_runs_over_several_values(ctx):
+    """Values far below the queries' round to the same difference: for a
+    query near 0.75 every tiny value gives e = 0.75, so one run of equal
+    distance spans many distinct values (emitted by index, not by value);
+    -0 and +0 mixed in as well."""
+    rng = np.random.default_rng(5)
+    H, W, K, R = 24, 60, 30, 3
+    tiny = (rng.random((H, W)) * 1e-9).astype(np.float32)
+    pc1 = np.where(rng.random((H, W)) < 0.6, tiny, np.float32(0.75)).astype(np.float32)
+    pc1[rng.random((H, W)) < 0.05] = np.float32(-0.0)
+    pc1[rng.random((H, W)) < 0.05] = np.float32(0.0)
+    _, prob = inputs.g_unif(H, W, 6)
+    check(ctx, "several-values", pc1, prob, K, R)
+
+
+def test_negative_values_and_ends_of_band(ctx):
+    """Negative and positive values; the frame's extreme values are queries
+    whose insertion point is an end of the sorted band."""
+    rng = np.random.default_rng(8)
+    H, W, K, R = 30, 50, 24, 6
+    pc1 = rng.normal(0, 3, size=(H, W)).astype(np.float32)
+    pc1[0, 0], pc1[H - 1, W - 1] = -100.0, 100.0
+    _, prob = inputs.g_unif(H, W, 7)
+    check(ctx, "negative", pc1, prob, K, R)
+
+
+@pytest.mark.parametrize("H,W,K,R", [(1, 200, 50, 3), (300, 1, 15, 7), (9, 11, 99 // 9, 0),
+                                     (5, 13, 65 // 5, 100)])
+def test_degenerate_shapes(ctx, H, W, K, R):
+    """One row, one column, R = 0 (the band is the query's own row, K up to
+    W), R beyond the frame (every pixel a candidate)."""
+    K = min(K, 64, min(R + 1, H) * W)  # no larger than the edge rows' band
+    pc1, prob = inputs.g_brain(H, W, 2 + W)
+    check(ctx, "degenerate", pc1, prob, K, R)
+
+
+def test_smallest_band_equals_k(ctx):
+    """K = the first row's band (R + 1 rows x W): the query takes every candidate."""
+    H, W, R = 12, 8, 3
+    K = (R + 1) * W  # 32
+    pc1, prob = inputs.g_unif(H, W, 9)
+    check(ctx, "K=band", pc1, prob, K, R)
+
+
+@pytest.mark.parametrize("W", [16384, 16385])
+def test_band_at_lds_capacity(ctx, W):
+    """R = 0 and W = 16,384: the band fills the 16,384 keys of LDS (16 keys
+    per thread); one pixel more and the general kernel runs instead."""
+    H, K = 3, 20
+    pc1, prob = inputs.g_unif(H, W, 11)
+    check(ctx, f"capacity W={W}", pc1, prob, K, 0)
+
+
+def test_band_capacity_many_rows(ctx):
+    """15 rows x 1092 columns = 16,380 keys per band (R = 7)."""
+    H, W, K, R = 20, 1092, 40, 7
+    pc1, prob = inputs.g_brain(H, W, 12)
+    check(ctx, "capacity R=7", pc1, prob, K, R)
