@@ -13,10 +13,10 @@
 //      keys in LDS: each thread sorts the T <= 16 keys it loaded in
 //      registers (a bitonic network), then ten merge-path rounds double the
 //      sorted runs (each thread finds its output range with one binary search
-//      along the merge diagonal, loads the next T keys of both runs, keeps
-//      the T smallest with a bitonic half-cleaner network in registers, and
-//      writes them back after a barrier, so the merge needs no second
-//      buffer); keys sit in LDS at XOR-swizzled positions (bank conflicts);
+//      along the merge diagonal, merges T keys into registers, and writes
+//      them back after a barrier, so the merge needs no second buffer); keys
+//      sit in LDS at XOR-swizzled positions, which spreads a wavefront's
+//      stores of 16 consecutive keys per lane over the banks;
 //   2. each lane takes one query pixel: a binary search finds where I_q falls
 //      in the sorted band; two cursors walk outward (values below and above
 //      I_q), taking at each step the whole run of candidates whose distance
@@ -125,26 +125,19 @@ __device__ __forceinline__ void sort_band(uint64_t* keys, int T, uint64_t (&v)[S
             if (keys[sw(bA + mid)] <= keys[sw(bB + k - mid - 1)]) lo = mid + 1;
             else hi = mid;
         }
-        // the outputs are the T smallest of A[i .. i+T) and B[j .. j+T):
-        // load both (independent loads), then keep the lower half of the
-        // bitonic sequence A ++ reversed B and sort it
-        const int i = lo, j = k - lo;
-        uint64_t a[SP_T], b[SP_T];
+        int i = lo, j = k - lo;
+        uint64_t a = i < s ? keys[sw(bA + i)] : SP_PAD, b = j < s ? keys[sw(bB + j)] : SP_PAD;
 #pragma unroll
         for (int o = 0; o < SP_T; ++o) {
-            a[o] = o < T && i + o < s ? keys[sw(bA + i + o)] : SP_PAD;
-            b[o] = o < T && j + o < s ? keys[sw(bB + j + o)] : SP_PAD;
-        }
-#pragma unroll
-        for (int o = 0; o < SP_T; ++o) v[o] = min(a[o], b[SP_T - 1 - o]);
-#pragma unroll
-        for (int h = SP_T / 2; h > 0; h >>= 1) {
-#pragma unroll
-            for (int o = 0; o < SP_T; ++o) {
-                if ((o & h) == 0) {
-                    const uint64_t x0 = v[o], x1 = v[o + h];
-                    v[o] = min(x0, x1);
-                    v[o + h] = max(x0, x1);
+            if (o < T) {
+                const bool ta = j >= s || (i < s && a <= b);
+                v[o] = ta ? a : b;
+                if (ta) {
+                    ++i;
+                    a = i < s ? keys[sw(bA + i)] : SP_PAD;
+                } else {
+                    ++j;
+                    b = j < s ? keys[sw(bB + j)] : SP_PAD;
                 }
             }
         }
@@ -247,44 +240,11 @@ spectral_filter_kernel(FrameDesc f, int T) {
             ++k;
         };
         const uint32_t NONE = 0xffffffffu;  // above every distance pattern
-        // the cursors' keys and distances, and the keys one further out, kept
-        // in registers: in the common case (one candidate at the smaller
-        // distance) a step reads one key, whose value the next step needs
-        uint64_t kL = 0, kR = 0, kL2 = 0, kR2 = 0;
-        uint32_t dL = NONE, dR = NONE;
-        auto reload = [&]() __attribute__((always_inline)) {
-            kL = L >= 0 ? keys[sw(L)] : 0;
-            kR = Rc < n ? keys[sw(Rc)] : 0;
-            kL2 = L >= 1 ? keys[sw(L - 1)] : 0;
-            kR2 = Rc + 1 < n ? keys[sw(Rc + 1)] : 0;
-            dL = L >= 0 ? dist0(x, key_value(kL)) : NONE;
-            dR = Rc < n ? dist0(x, key_value(kR)) : NONE;
-        };
-        reload();
         while (k < K) {
+            const uint32_t dL = L >= 0 ? dist0(x, key_value(keys[sw(L)])) : NONE;
+            const uint32_t dR = Rc < n ? dist0(x, key_value(keys[sw(Rc)])) : NONE;
             const uint32_t dm = min(dL, dR);
             if (dm == NONE) break;  // the band holds fewer than K pixels (not a valid frame)
-            if (dL == dm && dR != dm) {
-                const uint32_t dL2 = L >= 1 ? dist0(x, key_value(kL2)) : NONE;
-                if (dL2 != dm) {  // a run of one, below
-                    emit(kL, dm);
-                    --L;
-                    kL = kL2;
-                    dL = dL2;
-                    kL2 = L >= 1 ? keys[sw(L - 1)] : 0;
-                    continue;
-                }
-            } else if (dR == dm && dL != dm) {
-                const uint32_t dR2 = Rc + 1 < n ? dist0(x, key_value(kR2)) : NONE;
-                if (dR2 != dm) {  // a run of one, above
-                    emit(kR, dm);
-                    ++Rc;
-                    kR = kR2;
-                    dR = dR2;
-                    kR2 = Rc + 1 < n ? keys[sw(Rc + 1)] : 0;
-                    continue;
-                }
-            }
             // the run of distance dm on each side: [aL, L] and [Rc, bR]
             int aL = L + 1, bR = Rc - 1;
             if (dL == dm) {
@@ -350,7 +310,6 @@ spectral_filter_kernel(FrameDesc f, int T) {
             }
             L = aL - 1;
             Rc = bR + 1;
-            reload();
         }
         flush(nring);
         // Eq. 2 and the class map
