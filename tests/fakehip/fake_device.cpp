@@ -7,6 +7,7 @@
 // outputs.  A configurable delay per pixel stands in for the kernel's time.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cstring>
@@ -86,6 +87,19 @@ int launch_filter_frame(const FrameDesc& f, const LaunchCfg& cfg, void* stream) 
     const int rows = cfg.rows, cols = cfg.cols;
     const uint32_t nt = (uint32_t)((f.H + rows - 1) / rows) * (uint32_t)((f.W + cols - 1) / cols);
     return fakehip::enqueue((hipStream_t)stream, [d, rows, cols, nt] { run_tiles(d, rows, cols, 0, nt); });
+}
+
+// lambda = 0 selection: the same applicability rule as the device's; the
+// fake runs it as one 1 x 8 tiling of the frame (the oracle either way)
+bool spectral_fits(const FrameDesc& f) {
+    const int64_t rows = std::min<int64_t>((int64_t)2 * f.R + 1, f.H);
+    return f.lambda == 0.0f && rows * f.W <= 16384;
+}
+
+int launch_spectral_frame(const FrameDesc& f, void* stream) {
+    const FrameDesc d = f;
+    const uint32_t nt = (uint32_t)f.H * (uint32_t)((f.W + 7) / 8);
+    return fakehip::enqueue((hipStream_t)stream, [d, nt] { run_tiles(d, 1, 8, 0, nt); });
 }
 
 int launch_filter_items(const FrameDesc* d_frames, const uint32_t* d_task_start,
