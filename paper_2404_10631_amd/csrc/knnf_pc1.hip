@@ -212,9 +212,23 @@ pc1_normalise(const double* __restrict__ ws, int64_t npix, const double* __restr
     const double lo = pair[0], hi = pair[1];
     const bool flat = !(hi > lo);
     const double range = hi - lo;
+    // four pixels per thread and step, their loads issued together (one at a
+    // time, each step waited for its load: the large cubes' passes were
+    // latency-bound)
     const int64_t nthreads = (int64_t)gridDim.x * PC1_THREADS;
-    for (int64_t p = (int64_t)blockIdx.x * PC1_THREADS + threadIdx.x; p < npix; p += nthreads)
-        out[p] = flat ? 0.0f : (float)((ws[p] - lo) / range);
+    for (int64_t p = (int64_t)blockIdx.x * PC1_THREADS + threadIdx.x; p < npix; p += 4 * nthreads) {
+        double x[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t pk = p + k * nthreads;
+            x[k] = pk < npix ? ws[pk] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t pk = p + k * nthreads;
+            if (pk < npix) out[pk] = flat ? 0.0f : (float)((x[k] - lo) / range);
+        }
+    }
 }
 
 }  // namespace
