@@ -20,10 +20,12 @@
 // Work decomposition (not the paper's; designed for 64-wide wavefronts):
 //   * One wavefront task = a tile of QR x QC query pixels (default 1 x 8).
 //     Per-query state lives in VGPRs and a small per-wavefront LDS block.
-//   * pass A (bound): the 64 candidates of a compact block around each query
-//     (8 rows x 8 columns where the window allows) are evaluated and sorted
-//     for all Q queries at once by a segmented bitonic network; the K-th
-//     distance d_K bounds the query's final K-th key from above.
+//   * pass A (bound): the 128 candidates (8-query tiles; 64 for 16-query
+//     tiles) of a compact block around each query (8 rows x 16 columns where
+//     the window allows) are evaluated and sorted for all Q queries at once
+//     by a segmented bitonic network; the K-th distance d_K bounds the
+//     query's final K-th key from above.  The larger block's tighter bound
+//     lets fewer candidates through the scan than an 8 x 8 block's.
 //   * pass B (collect): candidates with d <= d_K are appended to a per-query
 //     LDS buffer with ballot + mbcnt; a full buffer is merged into a sorted
 //     per-query list, which tightens the bound.  Two scans:
@@ -236,16 +238,16 @@ __device__ __forceinline__ void seg_halves_u32(uint32_t (&x)[E], int lp) {
     }
 }
 
-template <int E, int KS>
+template <int E, int KS, int SEG = WAVE>
 __device__ __forceinline__ void seg_stage_u32(uint32_t (&x)[E], int lp) {
     seg_mirror_u32<E, KS>(x, lp);
     seg_halves_u32<E, KS, KS / 4>(x, lp);
-    if constexpr (KS < WAVE) seg_stage_u32<E, KS * 2>(x, lp);
+    if constexpr (KS < SEG) seg_stage_u32<E, KS * 2, SEG>(x, lp);
 }
 
-template <int E>
+template <int E, int SEG = WAVE>
 __device__ __forceinline__ void seg_sort_u32(uint32_t (&x)[E], int lp) {
-    seg_stage_u32<E, 2>(x, lp);
+    seg_stage_u32<E, 2, SEG>(x, lp);
 }
 
 // Per-wavefront LDS state of one tile of QR x QC query pixels.
@@ -541,7 +543,8 @@ __device__ __forceinline__ float gather_add(float s, const char* __restrict__ pb
 }
 
 // Process one tile: query pixels (r0 + qr, c0 + qc), qr < QR, qc < QC.
-template <int QR, int QC, bool PRUNE>
+// NA: pass-A block candidates per query (128 or 64; 64 for 16-query tiles).
+template <int QR, int QC, bool PRUNE, int NA = (QR * QC == 8 ? 128 : WAVE)>
 __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const FrameDesc& f, int r0,
                                              int c0, int lpr) {
     constexpr int Q = QR * QC;
@@ -558,8 +561,11 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
     // ---- pass A.  The K-th smallest distance d_K of a compact block bounds
     // the query's final K-th key from above by (d_K, max index).  All Q
     // blocks are evaluated and sorted together: segment q of the wavefront
-    // holds query q's 64 block candidates, Q per lane.
-    constexpr int E = Q, P = WAVE / Q;
+    // (P lanes) holds query q's NA block candidates, EA per lane.
+    constexpr int E = Q, P = WAVE / Q;          // final selection: 64 slots per query
+    constexpr int EA = NA / P;                  // pass-A candidates per lane
+    constexpr int LNA = NA == 128 ? 7 : 6;
+    static_assert(NA == WAVE || (NA == 128 && Q == 8), "pass-A block size");
     const int sq = L / P, lp = L % P;  // this lane's query (segment) and slot in it
     const int sqr = sq / QC, sqc = sq % QC;
     const bool sok = sqr < nqr && sqc < nqc;
@@ -569,7 +575,7 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
         const int nr = i1w - i0w + 1;
         const int lbr = nr >= 8 ? 3 : (nr >= 4 ? 2 : (nr >= 2 ? 1 : 0));
         const int br = 1 << lbr;
-        const int lbc = 6 - lbr;
+        const int lbc = LNA - lbr;
         const int bc = 1 << lbc;
         const int rb = min(max(r - br / 2, i0w), i1w - br + 1);
         const int cb = max(0, min(c - bc / 2, W - bc));
@@ -581,34 +587,54 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
         // columns of one row per load, so a load touches few cache lines.
         // Every lane loads (columns past the right edge clamped and given
         // +inf; rows rb .. rb+br-1 are inside the frame even for queries off
-        // its bottom edge), so all E loads are in flight together.
-        uint32_t x[E];
-        float pv[E];
-        if (E == 8 && W >= 8 && !ballot(lbr != 3)) {
+        // its bottom edge), so all EA loads are in flight together.
+        uint32_t x[EA];
+        float pv[EA];
+        if (EA == 8 && NA == WAVE && W >= 8 && !ballot(lbr != 3)) {
             // every block is 8 x 8 (P = 8): element u * 8 + lp is row rb + u,
             // column cb + lp < W, so a lane's column term is computed once
             const int j = cb + lp;
             const uint32_t o = (uint32_t)rb * (uint32_t)W + (uint32_t)j;
 #pragma unroll
-            for (int u = 0; u < E; ++u) pv[u] = pc1[o + (uint32_t)u * (uint32_t)W];
+            for (int u = 0; u < EA; ++u) pv[u] = pc1[o + (uint32_t)u * (uint32_t)W];
             const float b = fcq - feat(lam, j);
 #pragma unroll
-            for (int u = 0; u < E; ++u) {
+            for (int u = 0; u < EA; ++u) {
                 const float a = frq - feat(lam, rb + u);
                 const float ee = iqs - pv[u];
                 const uint32_t d = __float_as_uint(fmaf(ee, ee, fmaf(b, b, a * a)));
                 x[u] = sok ? d : 0x7f800000u;
             }
+        } else if (EA == 16 && NA == 128 && W >= 16 && !ballot(lbr != 3)) {
+            // every block is 8 x 16 (P = 8): element u * 8 + lp is row
+            // rb + u / 2, column cb + 8 (u % 2) + lp < W, so a lane has two
+            // column terms and each row term serves two elements
+            const int j = cb + lp;
+            const uint32_t o = (uint32_t)rb * (uint32_t)W + (uint32_t)j;
+#pragma unroll
+            for (int u = 0; u < EA; ++u)
+                pv[u] = pc1[o + (uint32_t)(u >> 1) * (uint32_t)W + (uint32_t)(8 * (u & 1))];
+            const float b0 = fcq - feat(lam, j), b1 = fcq - feat(lam, j + 8);
+#pragma unroll
+            for (int u = 0; u < EA; u += 2) {
+                const float a = frq - feat(lam, rb + (u >> 1));
+                const float a2 = a * a;
+                const float e0 = iqs - pv[u], e1 = iqs - pv[u + 1];
+                const uint32_t d0 = __float_as_uint(fmaf(e0, e0, fmaf(b0, b0, a2)));
+                const uint32_t d1 = __float_as_uint(fmaf(e1, e1, fmaf(b1, b1, a2)));
+                x[u] = sok ? d0 : 0x7f800000u;
+                x[u + 1] = sok ? d1 : 0x7f800000u;
+            }
         } else {
 #pragma unroll
-            for (int u = 0; u < E; ++u) {
+            for (int u = 0; u < EA; ++u) {
                 const int e = u * P + lp;
                 const int i = rb + (e >> lbc);
                 const int j = min(cb + (e & (bc - 1)), W - 1);
                 pv[u] = pc1[(uint32_t)i * (uint32_t)W + (uint32_t)j];
             }
 #pragma unroll
-            for (int u = 0; u < E; ++u) {
+            for (int u = 0; u < EA; ++u) {
                 const int e = u * P + lp;
                 const int i = rb + (e >> lbc);
                 const int j = cb + (e & (bc - 1));
@@ -620,20 +646,20 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
             }
         }
         if (lp == 0) S.iq[sq] = iqs;
-        seg_sort_u32<E>(x, lp);
-        // the segment's element K - 1 (lane (K-1) / E, register (K-1) % E) is
+        seg_sort_u32<EA, NA>(x, lp);
+        // the segment's element K - 1 (lane (K-1) / EA, register (K-1) % EA) is
         // the bound; only that lane writes it
-        const int uk = (K - 1) % E;
+        const int uk = (K - 1) % EA;
         uint32_t dk = x[0];
 #pragma unroll
-        for (int u = 1; u < E; ++u) dk = u == uk ? x[u] : dk;
-        if (lp == (K - 1) / E) S.tauhi[sq] = sok ? dk : 0u;
+        for (int u = 1; u < EA; ++u) dk = u == uk ? x[u] : dk;
+        if (lp == (K - 1) / EA) S.tauhi[sq] = sok ? dk : 0u;
         wave_sync();
     }
 
     // Work counter (only reported when f.stats is set): candidate distances
-    // evaluated for on-frame queries; pass A counts its 64 block slots.
-    unsigned long long pairs = (unsigned long long)(nqr * nqc) * WAVE;
+    // evaluated for on-frame queries; pass A counts its NA block slots.
+    unsigned long long pairs = (unsigned long long)(nqr * nqc) * NA;
 
     // Uniform per-query values live in VGPRs (read from LDS) to keep the
     // scalar register file free for loop state.  Queries off the frame have
@@ -1025,7 +1051,8 @@ filter_batch_kernel(const FrameDesc* __restrict__ frames, const uint32_t* __rest
             const uint32_t ntc = (uint32_t)((f.W + QC - 1) / QC);
             const int band = (int)(s / ntc);
             const int tc = (int)(s - (uint32_t)band * ntc);
-            process_tile<QR, QC, PRUNE>(lds[w], f, band * QR, tc * QC, lpr);
+            // the claim loop's registers leave no room for 128-candidate blocks
+            process_tile<QR, QC, PRUNE, WAVE>(lds[w], f, band * QR, tc * QC, lpr);
         }
     }
 }
