@@ -116,10 +116,11 @@ typedef struct knnf_ctx knnf_ctx;
  *                           search.  With lambda = 0 (the spectral distance
  *                           alone) a single-frame call (knnf_filter) under
  *                           this search runs a 1-D selection instead when the
- *                           band of 2R + 1 rows (clipped to H) holds at most
- *                           16,384 pixels: each query row's band is sorted by
- *                           PC1 value and each query walks outward from its
- *                           own value; same outputs again.  Its launches
+ *                           band of 2R + 2 rows (clipped to H) holds at most
+ *                           16,384 pixels: the band of two query rows'
+ *                           windows is sorted by PC1 value and each query
+ *                           walks outward from its own value over its own
+ *                           window's pixels; same outputs again.  Its launches
  *                           leave the work counters (knnf_stats_*) unchanged.
  */
 typedef enum { KNNF_SEARCH_EXHAUSTIVE = 0, KNNF_SEARCH_PRUNED = 1 } knnf_search;

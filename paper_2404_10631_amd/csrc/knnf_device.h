@@ -37,8 +37,8 @@ int launch_filter_batch(const FrameDesc* d_frames, const uint32_t* d_task_start,
                         uint32_t* d_counter, const LaunchCfg& cfg, int grid_blocks, void* stream);
 // The filter at lambda = 0 as a 1-D selection in each query row's band sorted
 // by value (defined in knnf_spectral.hip): applicable when spectral_fits(f)
-// (lambda == 0 and the band of 2R + 1 rows, clipped to H, holds at most
-// 16,384 pixels); same outputs as the scans.
+// (lambda == 0 and the band of 2R + 2 rows, clipped to H, that serves two
+// query rows holds at most 16,384 pixels); same outputs as the scans.
 bool spectral_fits(const FrameDesc& f);
 int launch_spectral_frame(const FrameDesc& f, void* stream);
 // Zero the batched kernel's claim counter.

@@ -6,29 +6,33 @@
 // d = fl32(e * e), e = fl32(I_q - I_p): a function of the PC1 values alone,
 // and a monotone one on each side of I_q (binary32 subtraction and squaring
 // round monotonically).  The candidates of q are the pixels of rows
-// max(0, r - R) .. min(H - 1, r + R), every column: the same set (the "band")
-// for every pixel of query row r.  So the K nearest are found as a 1-D
-// selection in the band sorted by value:
-//   1. one workgroup per query row sorts the band's (value, linear index)
-//      keys in LDS: each thread sorts the T <= 16 keys it loaded in
-//      registers (a bitonic network), then ten merge-path rounds double the
-//      sorted runs (each thread finds its output range with one binary search
-//      along the merge diagonal, merges T keys into registers, and writes
-//      them back after a barrier, so the merge needs no second buffer); keys
-//      sit in LDS at XOR-swizzled positions, which spreads a wavefront's
-//      stores of 16 consecutive keys per lane over the banks;
-//   2. each lane takes one query pixel: a binary search finds where I_q falls
-//      in the sorted band; two cursors walk outward (values below and above
-//      I_q), taking at each step the whole run of candidates whose distance
-//      equals the smaller of the two cursors' distances (a run's extent is
-//      found by a binary search, since the distance is monotone on each
-//      side), so the candidates come out in ascending distance; within a run,
-//      ascending linear index.  A run whose values are all equal on each side
-//      is already in index order in the sorted band (keys sort by value, then
-//      index), and two such runs merge in index order; a run spanning several
-//      values (rounding of the subtraction can give distinct values the same
-//      distance) is emitted by repeated minimum.  That is the strict (d, idx)
-//      order of the general kernels, so the neighbour lists are the same;
+// max(0, r - R) .. min(H - 1, r + R), every column: the same set for every
+// pixel of query row r.  So the K nearest are found as a 1-D selection in
+// a band sorted by value; one workgroup serves two query rows r0, r0 + 1
+// and sorts the band of both windows (2R + 2 rows, clipped):
+//   1. the workgroup sorts the band's (value, linear index) keys in LDS:
+//      each thread sorts the T <= 16 keys it loaded in registers (a bitonic
+//      network), then ten merge-path rounds double the sorted runs (each
+//      thread finds its output range with one binary search along the merge
+//      diagonal, merges T keys into registers, and writes them back after a
+//      barrier, so the merge needs no second buffer); keys sit in LDS at
+//      XOR-swizzled positions, which spreads a wavefront's stores of 16
+//      consecutive keys per lane over the banks;
+//   2. each lane takes one query pixel of the two rows: a binary search finds
+//      where I_q falls in the sorted band; two cursors walk outward (values
+//      below and above I_q), skipping the band row that lies outside the
+//      query's own window, taking at each step the whole run of candidates
+//      whose distance equals the smaller of the two cursors' distances (a
+//      run's extent is found by a binary search, since the distance is
+//      monotone on each side), so the candidates come out in ascending
+//      distance; within a run, ascending linear index.  A run whose values
+//      are all equal on each side is already in index order in the sorted
+//      band (keys sort by value, then index), so its keys inside the query's
+//      window are found by two binary searches on the index, and two such
+//      runs merge in index order; a run spanning several values (rounding of
+//      the subtraction can give distinct values the same distance) is
+//      emitted by repeated minimum.  That is the strict (d, idx) order of the
+//      general kernels, so the neighbour lists are the same;
 //   3. Eq. 2: the class sums add the neighbours' probabilities in that order
 //      from +0 (binary32), then one correctly rounded division by K; the
 //      class map is the argmax of the sums, lowest class on ties.  The
@@ -37,8 +41,11 @@
 //      predecessor's latency).
 // Work: O(n log n) per query row for the sort (n = band size) and
 // O(log n + K) per query, against O(n) distances per query for the scans.
-// Used for a single frame under the pruned search when lambda == 0 and the
-// band holds at most 16,384 pixels (it must fit in LDS).
+// Two query rows per workgroup halve the sorting per row and put the
+// W480 x H380 frame's 190 workgroups on the chip in one round (one row per
+// workgroup: 380 workgroups, two rounds, 0.255 against 0.183 ms).  Used for a
+// single frame under the pruned search when lambda == 0 and the band holds at
+// most 16,384 pixels (it must fit in LDS).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -152,10 +159,11 @@ __device__ __forceinline__ void sort_band(uint64_t* keys, int T, uint64_t (&v)[S
 __global__ void __launch_bounds__(SP_THREADS)
 spectral_filter_kernel(FrameDesc f, int T) {
     __shared__ uint64_t keys[SP_MAX];
-    const int r = blockIdx.x;
+    // two query rows per workgroup share one band: the rows of both windows
+    const int r0 = 2 * (int)blockIdx.x;
     const int t = threadIdx.x;
     const int W = f.W, C = f.C, K = f.K;
-    const int lo = max(0, r - f.R), hi = min(f.H - 1, r + f.R);
+    const int lo = max(0, r0 - f.R), hi = min(f.H - 1, r0 + 1 + f.R);
     const int n = (hi - lo + 1) * W;
     const uint32_t first = (uint32_t)lo * (uint32_t)W;
 
@@ -170,10 +178,21 @@ spectral_filter_kernel(FrameDesc f, int T) {
     }
     sort_band(keys, T, v);
 
-    // ---- 2. + 3. one lane per query pixel of row r
+    // ---- 2. + 3. one lane per query pixel of rows r0 and r0 + 1
     const float* __restrict__ prob = f.prob;
     const bool vec4 = C % 4 == 0 && ((uintptr_t)prob & 15) == 0;
-    for (int c = t; c < W; c += SP_THREADS) {
+    for (int qi = t; qi < 2 * W; qi += SP_THREADS) {
+        const int qr = qi >= W ? 1 : 0;
+        const int r = r0 + qr, c = qi - qr * W;
+        if (r >= f.H) break;
+        // the query's own window as band offsets [lo_q, hi_q): keys of the
+        // band's other rows are skipped
+        const int lo_q = (max(0, r - f.R) - lo) * W;
+        const int hi_q = (min(f.H - 1, r + f.R) - lo + 1) * W;
+        auto valid = [&](int p) __attribute__((always_inline)) {
+            const int e = (int)(key_index(keys[sw(p)]) - first);
+            return e >= lo_q && e < hi_q;
+        };
         const uint32_t q = (uint32_t)r * (uint32_t)W + (uint32_t)c;
         const float x = f.pc1[q];
         // first key whose value is >= x
@@ -241,6 +260,8 @@ spectral_filter_kernel(FrameDesc f, int T) {
         };
         const uint32_t NONE = 0xffffffffu;  // above every distance pattern
         while (k < K) {
+            while (L >= 0 && !valid(L)) --L;
+            while (Rc < n && !valid(Rc)) ++Rc;
             const uint32_t dL = L >= 0 ? dist0(x, key_value(keys[sw(L)])) : NONE;
             const uint32_t dR = Rc < n ? dist0(x, key_value(keys[sw(Rc)])) : NONE;
             const uint32_t dm = min(dL, dR);
@@ -271,35 +292,61 @@ spectral_filter_kernel(FrameDesc f, int T) {
                     bR = b0;
                 }
             }
-            const int tL = L - aL + 1, tR = bR - Rc + 1;
-            const int m = min(tL + tR, K - k);
-            const bool oneL = tL == 0 || (keys[sw(aL)] >> 32) == (keys[sw(L)] >> 32);
-            const bool oneR = tR == 0 || (keys[sw(Rc)] >> 32) == (keys[sw(bR)] >> 32);
+            const bool oneL = aL > L || (keys[sw(aL)] >> 32) == (keys[sw(L)] >> 32);
+            const bool oneR = Rc > bR || (keys[sw(Rc)] >> 32) == (keys[sw(bR)] >> 32);
             if (oneL && oneR) {
-                // each side one value: index order is storage order; merge
-                int i = aL, j = Rc;
+                // each side one value, so index order is storage order: keep
+                // the positions whose index lies in the query's window (two
+                // binary searches per side), then merge the two sides
+                const uint32_t ilo = first + (uint32_t)lo_q, ihi = first + (uint32_t)hi_q;
+                auto restrict_to = [&](int a, int b, int& sa, int& sb) __attribute__((always_inline)) {
+                    int p0 = a, p1 = b + 1;
+                    while (p0 < p1) {  // first position with index >= ilo
+                        const int mid = (p0 + p1) >> 1;
+                        if (key_index(keys[sw(mid)]) < ilo) p0 = mid + 1;
+                        else p1 = mid;
+                    }
+                    sa = p0;
+                    p1 = b + 1;
+                    while (p0 < p1) {  // first position with index >= ihi
+                        const int mid = (p0 + p1) >> 1;
+                        if (key_index(keys[sw(mid)]) < ihi) p0 = mid + 1;
+                        else p1 = mid;
+                    }
+                    sb = p0 - 1;
+                };
+                int la = aL, lb = L, ra = Rc, rb = bR;
+                if (aL <= L) restrict_to(aL, L, la, lb);
+                if (Rc <= bR) restrict_to(Rc, bR, ra, rb);
+                const int m = min(max(0, lb - la + 1) + max(0, rb - ra + 1), K - k);
+                int i = la, j = ra;
                 for (int e = 0; e < m; ++e) {
-                    const bool ti = j > bR || (i <= L && key_index(keys[sw(i)]) < key_index(keys[sw(j)]));
+                    const bool ti = j > rb || (i <= lb && key_index(keys[sw(i)]) < key_index(keys[sw(j)]));
                     emit(ti ? keys[sw(i)] : keys[sw(j)], dm);
                     if (ti) ++i;
                     else ++j;
                 }
             } else {
                 // several values in the run: ascending index by repeated minimum
+                // over the run's keys inside the query's window
+                int cntv = 0;
+                for (int p = aL; p <= L; ++p) cntv += valid(p) ? 1 : 0;
+                for (int p = Rc; p <= bR; ++p) cntv += valid(p) ? 1 : 0;
+                const int m = min(cntv, K - k);
                 int64_t last = -1;
                 for (int e = 0; e < m; ++e) {
                     uint32_t best = 0xffffffffu;
                     uint64_t bk = 0;
                     for (int p = aL; p <= L; ++p) {
                         const uint32_t ix = key_index(keys[sw(p)]);
-                        if ((int64_t)ix > last && ix <= best) {
+                        if ((int64_t)ix > last && ix <= best && valid(p)) {
                             best = ix;
                             bk = keys[sw(p)];
                         }
                     }
                     for (int p = Rc; p <= bR; ++p) {
                         const uint32_t ix = key_index(keys[sw(p)]);
-                        if ((int64_t)ix > last && ix <= best) {
+                        if ((int64_t)ix > last && ix <= best && valid(p)) {
                             best = ix;
                             bk = keys[sw(p)];
                         }
@@ -333,17 +380,18 @@ spectral_filter_kernel(FrameDesc f, int T) {
 
 }  // namespace
 
+// Rows of the band one workgroup sorts: both query rows' windows.
+int64_t spectral_band_rows(const FrameDesc& f) { return std::min<int64_t>((int64_t)2 * f.R + 2, f.H); }
+
 bool spectral_fits(const FrameDesc& f) {
-    const int rows = (int)std::min<int64_t>((int64_t)2 * f.R + 1, f.H);
-    return f.lambda == 0.0f && (int64_t)rows * f.W <= SP_MAX;
+    return f.lambda == 0.0f && spectral_band_rows(f) * f.W <= SP_MAX;
 }
 
 int launch_spectral_frame(const FrameDesc& f, void* stream) {
-    const int rows = (int)std::min<int64_t>((int64_t)2 * f.R + 1, f.H);
-    const int64_t n = (int64_t)rows * f.W;
+    const int64_t n = spectral_band_rows(f) * f.W;
     int T = 1;
     while ((int64_t)T * SP_THREADS < n) T <<= 1;
-    hipLaunchKernelGGL(spectral_filter_kernel, dim3((uint32_t)f.H), dim3(SP_THREADS), 0,
+    hipLaunchKernelGGL(spectral_filter_kernel, dim3((uint32_t)((f.H + 1) / 2)), dim3(SP_THREADS), 0,
                        (hipStream_t)stream, f, T);
     return (int)hipGetLastError();
 }

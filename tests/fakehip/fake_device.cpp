@@ -92,7 +92,7 @@ int launch_filter_frame(const FrameDesc& f, const LaunchCfg& cfg, void* stream) 
 // lambda = 0 selection: the same applicability rule as the device's; the
 // fake runs it as one 1 x 8 tiling of the frame (the oracle either way)
 bool spectral_fits(const FrameDesc& f) {
-    const int64_t rows = std::min<int64_t>((int64_t)2 * f.R + 1, f.H);
+    const int64_t rows = std::min<int64_t>((int64_t)2 * f.R + 2, f.H);
     return f.lambda == 0.0f && rows * f.W <= 16384;
 }
 

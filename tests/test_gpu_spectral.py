@@ -7,8 +7,9 @@ probabilities within 1e-6.  The cases aim at what the selection does
 differently from the scans: the binary searches (queries at both ends of the
 band, values repeated many times), runs of equal distance (one value on each
 side, several values that round to the same distance), bands at and just past
-the LDS capacity (16,384 pixels; past it the general kernel runs), one-row
-and one-column frames, K equal to the smallest band.
+the LDS capacity (16,384 pixels for the two query rows of a workgroup; past
+it the general kernel runs), one-row and one-column frames and odd heights
+(a workgroup with one query row), K equal to the smallest band.
 """
 import sys
 
@@ -150,17 +151,20 @@ def test_smallest_band_equals_k(ctx):
     check(ctx, "K=band", pc1, prob, K, R)
 
 
-@pytest.mark.parametrize("W", [16384, 16385])
+@pytest.mark.parametrize("W", [8192, 8193])
 def test_band_at_lds_capacity(ctx, W):
-    """R = 0 and W = 16,384: the band fills the 16,384 keys of LDS (16 keys
-    per thread); one pixel more and the general kernel runs instead."""
+    """R = 0 and W = 8,192: the band of a workgroup's two query rows fills the
+    16,384 keys of LDS (16 keys per thread); one column more and the general
+    kernel runs instead.  Three rows: the second workgroup has one query row."""
     H, K = 3, 20
     pc1, prob = inputs.g_unif(H, W, 11)
     check(ctx, f"capacity W={W}", pc1, prob, K, 0)
 
 
-def test_band_capacity_many_rows(ctx):
-    """15 rows x 1092 columns = 16,380 keys per band (R = 7)."""
-    H, W, K, R = 20, 1092, 40, 7
+@pytest.mark.parametrize("W", [1024, 1025])
+def test_band_capacity_many_rows(ctx, W):
+    """R = 7: 16 band rows x 1024 columns = 16,384 keys (and one column past
+    the capacity)."""
+    H, K, R = 21, 40, 7
     pc1, prob = inputs.g_brain(H, W, 12)
-    check(ctx, "capacity R=7", pc1, prob, K, R)
+    check(ctx, f"capacity R=7 W={W}", pc1, prob, K, R)
