@@ -256,9 +256,13 @@ struct alignas(16) TileState {
     static constexpr int Q = QR * QC;
     union {
         uint64_t pend[Q][WAVE];  // keys of candidates that passed the bound, unsorted
-        float sums[Q][MAXC];     // class sums for the argmax (after the final selection)
+        float sums[Q][MAXC + 1]; // class sums for the argmax (after the final selection);
+                                 // the odd row stride spreads the queries over the banks
     };
-    uint32_t list[Q][WAVE];   // sorted top-K linear indices (first listn valid);
+    // sorted top-K linear indices (first listn valid); rows padded by 16
+    // bytes so that the queries' rows start on different banks (Eq. 2 reads
+    // the same entry of every query at once, the final selection stores them)
+    uint32_t list[Q][WAVE + 4];
                               // before the scan: pass-A block distances
     uint32_t tauhi[Q];        // distance bits of the current bound on the K-th key
     float iq[Q];              // I of each query pixel (NaN for pixels off the frame)
@@ -544,7 +548,9 @@ __device__ __forceinline__ float gather_add(float s, const char* __restrict__ pb
 
 // Process one tile: query pixels (r0 + qr, c0 + qc), qr < QR, qc < QC.
 // NA: pass-A block candidates per query (128 or 64; 64 for 16-query tiles).
-template <int QR, int QC, bool PRUNE, int NA = (QR * QC == 8 ? 128 : WAVE)>
+// NG: groups the NA candidates are split into for the bound (1, 2 or 4).
+template <int QR, int QC, bool PRUNE, int NA = (QR * QC == 8 ? 128 : WAVE),
+          int NG = (NA == 128 ? 2 : 1)>
 __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const FrameDesc& f, int r0,
                                              int c0, int lpr) {
     constexpr int Q = QR * QC;
@@ -558,14 +564,21 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
 
     if (L < Q) S.listn[L] = 0;
 
-    // ---- pass A.  The K-th smallest distance d_K of a compact block bounds
-    // the query's final K-th key from above by (d_K, max index).  All Q
-    // blocks are evaluated and sorted together: segment q of the wavefront
-    // (P lanes) holds query q's NA block candidates, EA per lane.
+    // ---- pass A.  Any set of block candidates of which at least K have a
+    // distance <= d bounds the query's final K-th key from above by
+    // (d, max index).  The block's NA candidates are split into NG groups of
+    // the same spatial spread; with m = ceil(K / NG), the largest of the
+    // groups' m-th smallest distances is such a d (NG = 1: the block's K-th
+    // smallest).  All Q blocks are evaluated and sorted together: segment q
+    // of the wavefront (P lanes) holds query q's NA block candidates, EA per
+    // lane; group g is the segment's lanes g*LG .. g*LG + LG - 1.
     constexpr int E = Q, P = WAVE / Q;          // final selection: 64 slots per query
     constexpr int EA = NA / P;                  // pass-A candidates per lane
     constexpr int LNA = NA == 128 ? 7 : 6;
+    constexpr int LG = P / NG, GS = NA / NG;    // lanes and candidates per group
     static_assert(NA == WAVE || (NA == 128 && Q == 8), "pass-A block size");
+    static_assert((NG == 1 || NG == 2 || NG == 4) && LG >= 1 && (WAVE + NG - 1) / NG <= GS,
+                  "pass-A groups");
     const int sq = L / P, lp = L % P;  // this lane's query (segment) and slot in it
     const int sqr = sq / QC, sqc = sq % QC;
     const bool sok = sqr < nqr && sqc < nqc;
@@ -590,10 +603,13 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
         // its bottom edge), so all EA loads are in flight together.
         uint32_t x[EA];
         float pv[EA];
+        // full blocks: lane lp takes block column offset jl (a permutation of
+        // 0..7), so that the columns of every group spread over the block
+        const int jl = NG * (lp % LG) + lp / LG;
         if (EA == 8 && NA == WAVE && W >= 8 && !ballot(lbr != 3)) {
             // every block is 8 x 8 (P = 8): element u * 8 + lp is row rb + u,
-            // column cb + lp < W, so a lane's column term is computed once
-            const int j = cb + lp;
+            // column cb + jl < W, so a lane's column term is computed once
+            const int j = cb + jl;
             const uint32_t o = (uint32_t)rb * (uint32_t)W + (uint32_t)j;
 #pragma unroll
             for (int u = 0; u < EA; ++u) pv[u] = pc1[o + (uint32_t)u * (uint32_t)W];
@@ -607,9 +623,9 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
             }
         } else if (EA == 16 && NA == 128 && W >= 16 && !ballot(lbr != 3)) {
             // every block is 8 x 16 (P = 8): element u * 8 + lp is row
-            // rb + u / 2, column cb + 8 (u % 2) + lp < W, so a lane has two
+            // rb + u / 2, column cb + 8 (u % 2) + jl < W, so a lane has two
             // column terms and each row term serves two elements
-            const int j = cb + lp;
+            const int j = cb + jl;
             const uint32_t o = (uint32_t)rb * (uint32_t)W + (uint32_t)j;
 #pragma unroll
             for (int u = 0; u < EA; ++u)
@@ -646,14 +662,21 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
             }
         }
         if (lp == 0) S.iq[sq] = iqs;
-        seg_sort_u32<EA, NA>(x, lp);
-        // the segment's element K - 1 (lane (K-1) / EA, register (K-1) % EA) is
-        // the bound; only that lane writes it
-        const int uk = (K - 1) % EA;
+        seg_sort_u32<EA, GS>(x, lp);
+        // each group's element m - 1 (group lane (m-1) / EA, register
+        // (m-1) % EA); the largest of the NG goes to the group-0 holder,
+        // which writes the bound
+        const int m = (K + NG - 1) / NG;
+        const int uk = (m - 1) % EA;
         uint32_t dk = x[0];
 #pragma unroll
         for (int u = 1; u < EA; ++u) dk = u == uk ? x[u] : dk;
-        if (lp == (K - 1) / EA) S.tauhi[sq] = sok ? dk : 0u;
+        if constexpr (NG > 1) {
+            dk = (lp % LG) == (m - 1) / EA ? dk : 0u;
+            if constexpr (LG == 2) dk = max(dk, xlane<2>(dk));
+            dk = max(dk, xlane<4>(dk));
+        }
+        if (lp == (m - 1) / EA) S.tauhi[sq] = sok ? dk : 0u;
         wave_sync();
     }
 
@@ -1052,7 +1075,7 @@ filter_batch_kernel(const FrameDesc* __restrict__ frames, const uint32_t* __rest
             const int band = (int)(s / ntc);
             const int tc = (int)(s - (uint32_t)band * ntc);
             // the claim loop's registers leave no room for 128-candidate blocks
-            process_tile<QR, QC, PRUNE, WAVE>(lds[w], f, band * QR, tc * QC, lpr);
+            process_tile<QR, QC, PRUNE, WAVE, 1>(lds[w], f, band * QR, tc * QC, lpr);
         }
     }
 }
