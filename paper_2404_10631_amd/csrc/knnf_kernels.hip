@@ -546,6 +546,27 @@ __device__ __forceinline__ float gather_add(float s, const char* __restrict__ pb
     return s;
 }
 
+// As gather_add, with 32-bit byte offsets from a wave-uniform base: v[u] is
+// the float at base + lst[u] * rowb + cb, for frames whose linear indices fit
+// 24 bits and whose probability array fits 2^32 bytes (one full-rate 24-bit
+// multiply-add per gather instead of a 64-bit one).
+template <int N>
+__device__ __forceinline__ float gather_add24(float s, const char* __restrict__ base,
+                                              const uint32_t* lst, uint32_t rowb, uint32_t cb) {
+    float v[N];
+#pragma unroll
+    for (int u = 0; u < N; u += 4) {
+        const uint4 id = *(const uint4*)(lst + u);
+        v[u + 0] = *(const float*)(base + (__umul24(id.x, rowb) + cb));
+        v[u + 1] = *(const float*)(base + (__umul24(id.y, rowb) + cb));
+        v[u + 2] = *(const float*)(base + (__umul24(id.z, rowb) + cb));
+        v[u + 3] = *(const float*)(base + (__umul24(id.w, rowb) + cb));
+    }
+#pragma unroll
+    for (int u = 0; u < N; ++u) s = s + v[u];
+    return s;
+}
+
 // Process one tile: query pixels (r0 + qr, c0 + qc), qr < QR, qc < QC.
 // NA: pass-A block candidates per query (128 or 64; 64 for 16-query tiles).
 // NG: groups the NA candidates are split into for the bound (1, 2 or 4).
@@ -964,20 +985,33 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
     // ---- Eq. 2: sums in neighbour order, one lane per (query, class).  The
     // neighbours' rows are L2-resident; up to 16 gathers are in flight.
     const uint32_t rowb = (uint32_t)C * 4u;  // bytes per probability row
+    const uint64_t npix = (uint64_t)H * (uint64_t)W;
+    const bool off24 = npix <= (1u << 24) && npix * rowb <= 0xFFFFFFFFull;
     for (int p = L; p < Q * C; p += WAVE) {
         const int q = p / C, cl = p - q * C;
         const int qr = q / QC, qc = q % QC;
         if (qr >= nqr || qc >= nqc) continue;
-        const char* __restrict__ pb = (const char*)(f.prob + cl);
         const uint32_t* lst = S.list[q];
         float s = 0.0f;
         int k = 0;
-        for (; k + 16 <= K; k += 16) s = gather_add<16>(s, pb, lst + k, rowb);
-        if (k + 8 <= K) {
-            s = gather_add<8>(s, pb, lst + k, rowb);
-            k += 8;
+        if (off24) {
+            const char* __restrict__ base = (const char*)f.prob;
+            const uint32_t cb = (uint32_t)cl * 4u;
+            for (; k + 16 <= K; k += 16) s = gather_add24<16>(s, base, lst + k, rowb, cb);
+            if (k + 8 <= K) {
+                s = gather_add24<8>(s, base, lst + k, rowb, cb);
+                k += 8;
+            }
+            for (; k < K; ++k) s = s + *(const float*)(base + (__umul24(lst[k], rowb) + cb));
+        } else {
+            const char* __restrict__ pb = (const char*)(f.prob + cl);
+            for (; k + 16 <= K; k += 16) s = gather_add<16>(s, pb, lst + k, rowb);
+            if (k + 8 <= K) {
+                s = gather_add<8>(s, pb, lst + k, rowb);
+                k += 8;
+            }
+            for (; k < K; ++k) s = s + *(const float*)(pb + (uint64_t)lst[k] * rowb);
         }
-        for (; k < K; ++k) s = s + *(const float*)(pb + (uint64_t)lst[k] * rowb);
         S.sums[q][cl] = s;
         const size_t pix = (size_t)(r0 + qr) * W + c0 + qc;
         f.out_prob[pix * C + cl] = s / (float)K;
