@@ -27,7 +27,8 @@
 // The loads of the next chunk are in flight while the current one is used.
 // The fused variant (PC1 = true) also accumulates the PC1 projection from the
 // same chunks, so the pipeline's two steps before the filter read the cube
-// once.
+// once.  knnf_svm on cubes whose pixel rows are not whole cache lines stages
+// linear runs of whole rows instead (svm_prob_lin_kernel).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -319,6 +320,129 @@ svm_prob_kernel(const float* __restrict__ cube, int64_t npix, int bands,
     svm_finish<C, SVM_THREADS, PC1>(first + tid, npix, f, pj, bias, A, B, out, band, ws, pairs);
 }
 
+// knnf_svm on cubes whose pixel rows are not whole 128-byte lines (bands * 4
+// not a multiple of 128, e.g. 100 bands): per-pixel band chunks split lines
+// between chunks and between neighbouring pixels, and a line evicted between
+// its two uses is fetched twice (1.6x the cube's bytes on the 1000 x 1000 x
+// 100 cube).  This variant reads the block's 256 pixels as 4 linear runs of
+// 64 whole pixel rows (each line once, in full), staged in LDS with a row
+// stride of S = 16 (mod 32) floats.  Four lanes share a pixel of a run: lane
+// part t takes the float4 pieces t, t+4, ... of the row (a quarter-
+// wavefront's 16-byte reads then cover all 64 banks), and a butterfly over
+// the four lanes completes the pixel's sums.  Lane part t keeps the sums of
+// run t, so thread 4 pl + t owns pixel 64 t + pl of the block for the
+// sigmoids and the coupling.  All weights are staged once, piece by piece.
+// The sums run in a different order than band by band (four interleaved
+// partial sums), which moves the binary64 results by rounding only.  (With
+// the PC1 projection added, the band-chunk kernel above measured faster, so
+// the fused call keeps it.)
+constexpr int LIN_RUN = 64;                     // pixels per linear run
+constexpr int LIN_MAX_BANDS = 128;
+constexpr int LIN_MAX_WEIGHTS = 2048;           // doubles of weights staged at once
+constexpr int LIN_MAX_C = 4;                    // more classes: the coupling's registers spill
+
+__host__ __device__ constexpr int lin_stride(int bands) {
+    return ((bands + 15) / 32) * 32 + 16;       // smallest S >= bands with S = 16 (mod 32)
+}
+// Doubles per piece of staged weights: the smallest >= 4 M that is 8 (mod
+// 16), so the four lanes of a quad (pieces k .. k+3) read on disjoint banks.
+__host__ __device__ constexpr int lin_piece(int m) { return ((4 * m + 7) / 16) * 16 + 8; }
+
+__device__ __forceinline__ double quad_sum(double v) {
+    // sum over the 4 lanes of a quad (xor 1, then xor 2), every lane gets it
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    v += __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0xB1, 0xF, 0xF, false),
+                          __builtin_amdgcn_update_dpp(lo, lo, 0xB1, 0xF, 0xF, false));
+    lo = __double2loint(v);
+    hi = __double2hiint(v);
+    return v + __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x4E, 0xF, 0xF, false),
+                                __builtin_amdgcn_update_dpp(lo, lo, 0x4E, 0xF, 0xF, false));
+}
+
+template <int C>
+__global__ void __launch_bounds__(SVM_THREADS) __attribute__((amdgpu_waves_per_eu(3)))
+svm_prob_lin_kernel(const float* __restrict__ cube, int64_t npix, int bands,
+                    const double* __restrict__ w, const double* __restrict__ bias,
+                    const double* __restrict__ A, const double* __restrict__ B,
+                    float* __restrict__ out) {
+    constexpr int M = C * (C - 1) / 2;
+    constexpr int PS = lin_piece(M);
+    constexpr int NLD = LIN_RUN * LIN_MAX_BANDS / 4 / SVM_THREADS;  // float4 loads per thread, max
+    extern __shared__ __attribute__((aligned(16))) double lin_smem[];
+    double* wl = lin_smem;                                 // bands / 4 pieces x PS
+    const int S = lin_stride(bands);
+    float* tile = (float*)(lin_smem + (bands >> 2) * PS);  // LIN_RUN x S
+    const int tid = threadIdx.x;
+    const int pl = tid >> 2, t = tid & 3;
+    const int64_t first = (int64_t)blockIdx.x * SVM_THREADS;
+    const int b4 = bands >> 2;                             // float4 pieces per pixel
+    const int nq = LIN_RUN * b4;                           // pieces per run
+    const float inv_b4 = 1.0f / (float)b4;
+
+    // weights by piece: wl[k * PS + m * 4 + e] is hyperplane m at band
+    // 4 k + e, so a piece's M x 4 weights are contiguous (16-byte LDS reads
+    // at constant offsets)
+    for (int e = tid; e < M * bands; e += SVM_THREADS) {
+        const int m = e / bands, bb = e - m * bands;
+        wl[(bb >> 2) * PS + m * 4 + (bb & 3)] = w[(int64_t)m * bands + bb];
+    }
+
+    // run r: pixels first + 64 r .. +63, read as one linear range of pieces
+    // (pixels past the cube read as 0 and are never written)
+    float4 v[NLD];
+    auto fetch = [&](int r) {
+        const int64_t p0 = first + (int64_t)LIN_RUN * r;
+        const char* src = (const char*)(cube + p0 * (int64_t)bands);
+        // pieces inside the run and the cube
+        const int lim = (int)min((int64_t)nq, max((int64_t)0, npix - p0) * b4);
+#pragma unroll
+        for (int i = 0; i < NLD; ++i) {
+            const int q = tid + SVM_THREADS * i;
+            v[i] = q < lim ? *(const float4*)(src + (uint32_t)q * 16u) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    double own[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) own[m] = 0.0;
+    fetch(0);
+#pragma unroll 1
+    for (int r = 0; r < SVM_THREADS / LIN_RUN; ++r) {
+#pragma unroll
+        for (int i = 0; i < NLD; ++i) {
+            const int q = tid + SVM_THREADS * i;
+            if (q < nq) {
+                // piece q is pixel q / b4 of the run, bands 4 (q % b4) ..
+                const int px = (int)(((float)q + 0.5f) * inv_b4);
+                *(float4*)(tile + px * S + 4 * (q - px * b4)) = v[i];
+            }
+        }
+        __syncthreads();
+        if (r + 1 < SVM_THREADS / LIN_RUN) fetch(r + 1);
+        double f[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) f[m] = 0.0;
+        const float* row = tile + pl * S;
+#pragma unroll 1
+        for (int k = t; k < b4; k += 4) {
+            const float4 xa = *(const float4*)(row + 4 * k);
+            const double x[4] = {(double)xa.x, (double)xa.y, (double)xa.z, (double)xa.w};
+            const double* wk = wl + k * PS;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int m = 0; m < M; ++m) f[m] = fma(wk[m * 4 + e], x[e], f[m]);
+        }
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            f[m] = quad_sum(f[m]);
+            own[m] = t == r ? f[m] : own[m];
+        }
+        __syncthreads();
+    }
+    svm_finish<C, SVM_THREADS, false>(first + LIN_RUN * t + pl, npix, own, 0.0, bias, A, B, out,
+                                      nullptr, nullptr, nullptr);
+}
+
 struct SvmArgs {
     const float* cube;
     int64_t npix;
@@ -333,11 +457,22 @@ int launch_c(const SvmArgs& a, void* stream, int* nblocks) {
     const hipStream_t st = (hipStream_t)stream;
     const int64_t blocks = (a.npix + SVM_THREADS - 1) / SVM_THREADS;
     const bool vec = a.bands % 4 == 0 && ((uintptr_t)a.cube & 15) == 0;
-    if (vec)
+    bool lin = false;
+    if constexpr (C <= LIN_MAX_C && !PC1) {
+        constexpr int M = C * (C - 1) / 2;
+        const int wd = a.bands / 4 * lin_piece(M);       // doubles of staged weights
+        lin = vec && (a.bands * 4) % 128 != 0 && a.bands <= LIN_MAX_BANDS && wd <= LIN_MAX_WEIGHTS;
+        if (lin) {
+            const size_t lds = (size_t)wd * 8 + (size_t)LIN_RUN * lin_stride(a.bands) * 4;
+            hipLaunchKernelGGL((svm_prob_lin_kernel<C>), dim3((uint32_t)blocks), dim3(SVM_THREADS),
+                               lds, st, a.cube, a.npix, a.bands, a.w, a.bias, a.A, a.B, a.out);
+        }
+    }
+    if (!lin && vec)
         hipLaunchKernelGGL((svm_prob_kernel<C, true, PC1>), dim3((uint32_t)blocks), dim3(SVM_THREADS),
                            0, st, a.cube, a.npix, a.bands, a.w, a.bias, a.A, a.B, a.out, a.mean,
                            a.vec, a.band, a.ws, a.pairs);
-    else
+    else if (!lin)
         hipLaunchKernelGGL((svm_prob_kernel<C, false, PC1>), dim3((uint32_t)blocks), dim3(SVM_THREADS),
                            0, st, a.cube, a.npix, a.bands, a.w, a.bias, a.A, a.B, a.out, a.mean,
                            a.vec, a.band, a.ws, a.pairs);

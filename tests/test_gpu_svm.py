@@ -5,9 +5,11 @@ Bar: both sides evaluate every step in binary64 and round once to binary32;
 the GPU sums the decision values and the coupling products in its own order,
 so values agree to a few binary64 ulps before the final rounding: every
 output within 1e-6 of the oracle's (in practice equal or one binary32 ulp
-apart).  Cases cover the 16-byte and the scalar staging paths, band counts
-that leave a partial 32-band chunk, pixel counts that leave a partial block,
-two to eight classes, and the full W 480 x H 380 x 128 and 1000 x 1000 x 100
+apart).  Cases cover the three staging paths (16-byte band chunks, scalar
+band chunks, and linear runs of whole pixel rows for rows that are not whole
+128-byte lines, up to four classes), band counts that leave a partial
+32-band chunk, pixel counts that leave a partial block or a partial run, two
+to eight classes, and the full W 480 x H 380 x 128 and 1000 x 1000 x 100
 cubes at every pixel.
 """
 import sys
@@ -83,6 +85,8 @@ CASES = [
     ("bands-124-C2", 5, 40, 124, 2, "brain"),
     ("one-pixel-100", 1, 1, 100, 4, "derma"),
     ("ragged-129-100", 1, 129, 100, 4, "derma"),
+    ("runs-700-100", 1, 700, 100, 4, "derma"),
+    ("C3-36", 17, 43, 36, 3, "brain"),
 ]
 
 
@@ -124,8 +128,8 @@ def test_svm_full_size_brain_cube(ctx):
 
 
 def test_svm_full_size_derma_cube(ctx):
-    """1000 x 1000, 100 bands (400-byte pixel rows: staging pieces straddle
-    cache lines), four classes: every pixel."""
+    """1000 x 1000, 100 bands (400-byte pixel rows, staged as linear runs of
+    whole rows), four classes: every pixel."""
     cube, _, _ = inputs.g_cube(1000, 1000, 100, 3, "derma")
     model = inputs.g_svm_model(4, 100, 4)
     say("svm full-size derma cube")

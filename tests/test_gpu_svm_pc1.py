@@ -97,6 +97,8 @@ CASES = [
     ("ragged-block", 1, 257, 128, 4, "brain"),
     ("bands-100-C8", 11, 29, 100, 8, "derma"),
     ("ragged-129-100", 1, 129, 100, 4, "derma"),
+    ("runs-700-100", 1, 700, 100, 4, "derma"),
+    ("C3-36", 17, 43, 36, 3, "brain"),
     ("bands-4", 13, 11, 4, 4, "derma"),
 ]
 
