@@ -640,7 +640,7 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
                 const float a = frq - feat(lam, rb + u);
                 const float ee = iqs - pv[u];
                 const uint32_t d = __float_as_uint(fmaf(ee, ee, fmaf(b, b, a * a)));
-                x[u] = sok ? d : 0x7f800000u;
+                x[u] = d;  // NaN bits for a query off the frame (segment unused)
             }
         } else if (EA == 16 && NA == 128 && W >= 16 && !ballot(lbr != 3)) {
             // every block is 8 x 16 (P = 8): element u * 8 + lp is row
@@ -659,8 +659,8 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
                 const float e0 = iqs - pv[u], e1 = iqs - pv[u + 1];
                 const uint32_t d0 = __float_as_uint(fmaf(e0, e0, fmaf(b0, b0, a2)));
                 const uint32_t d1 = __float_as_uint(fmaf(e1, e1, fmaf(b1, b1, a2)));
-                x[u] = sok ? d0 : 0x7f800000u;
-                x[u + 1] = sok ? d1 : 0x7f800000u;
+                x[u] = d0;  // NaN bits for a query off the frame (segment unused)
+                x[u + 1] = d1;
             }
         } else {
 #pragma unroll
@@ -688,10 +688,8 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
         // (m-1) % EA); the largest of the NG goes to the group-0 holder,
         // which writes the bound
         const int m = (K + NG - 1) / NG;
-        const int uk = (m - 1) % EA;
-        uint32_t dk = x[0];
-#pragma unroll
-        for (int u = 1; u < EA; ++u) dk = u == uk ? x[u] : dk;
+        const int uk = uni((m - 1) % EA);
+        uint32_t dk = x[uk];  // uniform register index
         if constexpr (NG > 1) {
             dk = (lp % LG) == (m - 1) / EA ? dk : 0u;
             if constexpr (LG == 2) dk = max(dk, xlane<2>(dk));
@@ -920,12 +918,16 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
         for (int u = 0; u < E; ++u) y[u] = x[u] < 0x7f800000u ? S.pend[sq][x[u] & 63u] : KEY_INF;
         // neighbours in sorted order: element lp*E + u, the next one is u + 1
         // or the next lane's element 0 (same segment while lp < P - 1)
+        // two neighbours share the distance part iff their keys differ in the
+        // slot bits only: 1 <= (a ^ b) <= 63 (keys of candidates are distinct;
+        // two empty slots, both 0x7f800000, give 0; a candidate next to an
+        // empty slot differs above bit 22)
         bool tie = false;
 #pragma unroll
-        for (int u = 0; u + 1 < E; ++u) tie |= (x[u] >> 6) == (x[u + 1] >> 6) && x[u] < 0x7f800000u;
+        for (int u = 0; u + 1 < E; ++u) tie |= (uint32_t)((x[u] ^ x[u + 1]) - 1u) < 63u;
         {
             const uint32_t nx = (uint32_t)__builtin_amdgcn_mov_dpp((int)x[0], 0x101, 0xF, 0xF, false);  // row_shl:1
-            tie |= lp < P - 1 && (x[E - 1] >> 6) == (nx >> 6) && x[E - 1] < 0x7f800000u;
+            tie |= lp < P - 1 && (uint32_t)((x[E - 1] ^ nx) - 1u) < 63u;
         }
         if (ballot(tie)) {
             for (;;) {
