@@ -603,6 +603,7 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
     const int sq = L / P, lp = L % P;  // this lane's query (segment) and slot in it
     const int sqr = sq / QC, sqc = sq % QC;
     const bool sok = sqr < nqr && sqc < nqc;
+    const bool off32 = (uint64_t)H * (uint64_t)W <= (1u << 30);  // band byte offsets fit 32 bits
     {
         const int r = r0 + sqr, c = c0 + sqc;
         const int i0w = max(0, r - R), i1w = min(H - 1, r + R);
@@ -642,15 +643,19 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
                 const uint32_t d = __float_as_uint(fmaf(ee, ee, fmaf(b, b, a * a)));
                 x[u] = d;  // NaN bits for a query off the frame (segment unused)
             }
-        } else if (EA == 16 && NA == 128 && W >= 16 && !ballot(lbr != 3)) {
+        } else if (EA == 16 && NA == 128 && W >= 16 && off32 && !ballot(lbr != 3)) {
             // every block is 8 x 16 (P = 8): element u * 8 + lp is row
             // rb + u / 2, column cb + 8 (u % 2) + jl < W, so a lane has two
-            // column terms and each row term serves two elements
+            // column terms and each row term serves two elements.  Byte
+            // offsets from the band's base fit 32 bits (off32): one add per
+            // row, the second column half as the load's immediate offset.
             const int j = cb + jl;
-            const uint32_t o = (uint32_t)rb * (uint32_t)W + (uint32_t)j;
+            const uint32_t o4 = ((uint32_t)rb * (uint32_t)W + (uint32_t)j) * 4u;
+            const char* __restrict__ pcb = (const char*)pc1;
 #pragma unroll
             for (int u = 0; u < EA; ++u)
-                pv[u] = pc1[o + (uint32_t)(u >> 1) * (uint32_t)W + (uint32_t)(8 * (u & 1))];
+                pv[u] = *(const float*)(pcb + (o4 + (uint32_t)(u >> 1) * (uint32_t)W * 4u) +
+                                        32u * (u & 1));
             const float b0 = fcq - feat(lam, j), b1 = fcq - feat(lam, j + 8);
 #pragma unroll
             for (int u = 0; u < EA; u += 2) {
@@ -907,8 +912,9 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
         uint32_t x[E];
 #pragma unroll
         for (int u = 0; u < E; ++u) {
-            // slot assignment rotated by segment: one read touches every bank
-            const int e = ((u + sq) % E) * P + lp;
+            // slot blocks permuted by segment (u ^ sq: E is a power of two and
+            // sq < E), so the segments' reads of one u spread over the banks
+            const int e = (u ^ sq) * P + lp;
             const uint32_t dh = (uint32_t)(S.pend[sq][e] >> 32);
             x[u] = (own && e < cq) ? ((min(dh, 0x7f7fffc0u) & ~63u) | (uint32_t)e) : 0x7f800000u;
         }
