@@ -250,6 +250,88 @@ __device__ __forceinline__ void seg_sort_u32(uint32_t (&x)[E], int lp) {
     seg_stage_u32<E, 2, SEG>(x, lp);
 }
 
+// ---- the same network on pairs of 16-bit keys: register r of lane L holds
+// element (L % P) * E + r of two independent segments, one in each half,
+// sorted together with packed unsigned 16-bit min / max (v_pk_min_u16,
+// v_pk_max_u16: integer instructions).  Cross-lane pairs keep min or max by
+// lane.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pk_min(uint32_t a, uint32_t b) {
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(__builtin_bit_cast(u16x2, a),
+                                                                  __builtin_bit_cast(u16x2, b)));
+}
+__device__ __forceinline__ uint32_t pk_max(uint32_t a, uint32_t b) {
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(u16x2, a),
+                                                                  __builtin_bit_cast(u16x2, b)));
+}
+__device__ __forceinline__ uint32_t pk_keep(uint32_t x, uint32_t p, bool upper) {
+    return upper ? pk_max(x, p) : pk_min(x, p);
+}
+
+template <int E, int KS>
+__device__ __forceinline__ void seg_mirror_pk(uint32_t (&x)[E], int lp) {
+    if constexpr (KS <= E) {
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            if (r & (KS / 2)) continue;
+            constexpr int M = KS - 1;
+            const uint32_t a = x[r], b = x[r ^ M];
+            x[r] = pk_min(a, b);
+            x[r ^ M] = pk_max(a, b);
+        }
+    } else {
+        const bool upper = (lp & (KS / (2 * E))) != 0;
+        uint32_t p[E];
+#pragma unroll
+        for (int r = 0; r < E; ++r) p[r] = lanex<KS / E - 1>(x[E - 1 - r]);
+#pragma unroll
+        for (int r = 0; r < E; ++r) x[r] = pk_keep(x[r], p[r], upper);
+    }
+}
+
+template <int E, int D>
+__device__ __forceinline__ void seg_half_pk(uint32_t (&x)[E], int lp) {
+    if constexpr (D < E) {
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            if (r & D) continue;
+            const uint32_t a = x[r], b = x[r | D];
+            x[r] = pk_min(a, b);
+            x[r | D] = pk_max(a, b);
+        }
+    } else {
+        const bool upper = (lp & (D / E)) != 0;
+#pragma unroll
+        for (int r = 0; r < E; ++r) x[r] = pk_keep(x[r], lanex<D / E>(x[r]), upper);
+    }
+}
+
+template <int E, int KS, int D>
+__device__ __forceinline__ void seg_halves_pk(uint32_t (&x)[E], int lp) {
+    if constexpr (D >= 1) {
+        seg_half_pk<E, D>(x, lp);
+        seg_halves_pk<E, KS, D / 2>(x, lp);
+    }
+}
+
+template <int E, int KS, int SEG>
+__device__ __forceinline__ void seg_stage_pk(uint32_t (&x)[E], int lp) {
+    seg_mirror_pk<E, KS>(x, lp);
+    seg_halves_pk<E, KS, KS / 4>(x, lp);
+    if constexpr (KS < SEG) seg_stage_pk<E, KS * 2, SEG>(x, lp);
+}
+
+template <int E, int SEG>
+__device__ __forceinline__ void seg_sort_pk(uint32_t (&x)[E], int lp) {
+    seg_stage_pk<E, 2, SEG>(x, lp);
+}
+
+// Two non-negative binary32 bit patterns (or +inf / NaN bits) as a pair of
+// 16-bit keys rounded up: key = ceil(d / 2^16), so d <= key << 16.
+__device__ __forceinline__ uint32_t pack_up(uint32_t lo, uint32_t hi) {
+    return ((lo + 0xffffu) >> 16) | ((hi + 0xffffu) & 0xffff0000u);
+}
+
 // Per-wavefront LDS state of one tile of QR x QC query pixels.
 template <int QR, int QC>
 struct alignas(16) TileState {
@@ -597,6 +679,7 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
     constexpr int EA = NA / P;                  // pass-A candidates per lane
     constexpr int LNA = NA == 128 ? 7 : 6;
     constexpr int LG = P / NG, GS = NA / NG;    // lanes and candidates per group
+    constexpr bool PK = NA == 128 && NG == 2;   // two groups as 16-bit key pairs
     static_assert(NA == WAVE || (NA == 128 && Q == 8), "pass-A block size");
     static_assert((NG == 1 || NG == 2 || NG == 4) && LG >= 1 && (WAVE + NG - 1) / NG <= GS,
                   "pass-A groups");
@@ -623,84 +706,149 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
         // Every lane loads (columns past the right edge clamped and given
         // +inf; rows rb .. rb+br-1 are inside the frame even for queries off
         // its bottom edge), so all EA loads are in flight together.
-        uint32_t x[EA];
-        float pv[EA];
-        // full blocks: lane lp takes block column offset jl (a permutation of
-        // 0..7), so that the columns of every group spread over the block
-        const int jl = NG * (lp % LG) + lp / LG;
-        if (EA == 8 && NA == WAVE && W >= 8 && !ballot(lbr != 3)) {
-            // every block is 8 x 8 (P = 8): element u * 8 + lp is row rb + u,
-            // column cb + jl < W, so a lane's column term is computed once
-            const int j = cb + jl;
-            const uint32_t o = (uint32_t)rb * (uint32_t)W + (uint32_t)j;
+        if constexpr (PK) {
+            // 128 candidates as 8 registers of 16-bit key pairs: group 0 in
+            // the low halves, group 1 in the high halves, each group's 64
+            // keys (8 per lane) sorted by one packed network
+            uint32_t xp[8];
+            if (W >= 16 && off32 && !ballot(lbr != 3)) {
+                // every block is 8 x 16: lane lp takes columns cb + 2 lp
+                // (group 0) and cb + 2 lp + 1 (group 1) of rows rb .. rb + 7,
+                // so both groups hold every row and alternate columns
+                const int j = cb + 2 * lp;
+                const uint32_t o4 = ((uint32_t)rb * (uint32_t)W + (uint32_t)j) * 4u;
+                const char* __restrict__ pcb = (const char*)pc1;
+                float p0[8], p1[8];
 #pragma unroll
-            for (int u = 0; u < EA; ++u) pv[u] = pc1[o + (uint32_t)u * (uint32_t)W];
-            const float b = fcq - feat(lam, j);
+                for (int u = 0; u < 8; ++u) {
+                    const char* row = pcb + (o4 + (uint32_t)u * (uint32_t)W * 4u);
+                    p0[u] = *(const float*)row;
+                    p1[u] = *(const float*)(row + 4);
+                }
+                const float b0 = fcq - feat(lam, j), b1 = fcq - feat(lam, j + 1);
 #pragma unroll
-            for (int u = 0; u < EA; ++u) {
-                const float a = frq - feat(lam, rb + u);
-                const float ee = iqs - pv[u];
-                const uint32_t d = __float_as_uint(fmaf(ee, ee, fmaf(b, b, a * a)));
-                x[u] = d;  // NaN bits for a query off the frame (segment unused)
+                for (int u = 0; u < 8; ++u) {
+                    const float a = frq - feat(lam, rb + u);
+                    const float a2 = a * a;
+                    const float e0 = iqs - p0[u], e1 = iqs - p1[u];
+                    // NaN bits for a query off the frame (segment unused)
+                    xp[u] = pack_up(__float_as_uint(fmaf(e0, e0, fmaf(b0, b0, a2))),
+                                    __float_as_uint(fmaf(e1, e1, fmaf(b1, b1, a2))));
+                }
+            } else {
+                // element e = u * 8 + lp of the block (u < 16): group 0 the
+                // elements u < 8, group 1 the rest
+                float pv[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const int e = u * P + lp;
+                    const int i = rb + (e >> lbc);
+                    const int j = min(cb + (e & (bc - 1)), W - 1);
+                    pv[u] = pc1[(uint32_t)i * (uint32_t)W + (uint32_t)j];
+                }
+                uint32_t x[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const int e = u * P + lp;
+                    const int i = rb + (e >> lbc);
+                    const int j = cb + (e & (bc - 1));
+                    const float a = frq - feat(lam, i);
+                    const float b = fcq - feat(lam, j);
+                    const float ee = iqs - pv[u];
+                    const uint32_t d = __float_as_uint(fmaf(ee, ee, fmaf(b, b, a * a)));
+                    x[u] = (sok && j < W) ? d : 0x7f800000u;  // +inf: no candidate
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) xp[u] = pack_up(x[u], x[u + 8]);
             }
-        } else if (EA == 16 && NA == 128 && W >= 16 && off32 && !ballot(lbr != 3)) {
-            // every block is 8 x 16 (P = 8): element u * 8 + lp is row
-            // rb + u / 2, column cb + 8 (u % 2) + jl < W, so a lane has two
-            // column terms and each row term serves two elements.  Byte
-            // offsets from the band's base fit 32 bits (off32): one add per
-            // row, the second column half as the load's immediate offset.
-            const int j = cb + jl;
-            const uint32_t o4 = ((uint32_t)rb * (uint32_t)W + (uint32_t)j) * 4u;
-            const char* __restrict__ pcb = (const char*)pc1;
-#pragma unroll
-            for (int u = 0; u < EA; ++u)
-                pv[u] = *(const float*)(pcb + (o4 + (uint32_t)(u >> 1) * (uint32_t)W * 4u) +
-                                        32u * (u & 1));
-            const float b0 = fcq - feat(lam, j), b1 = fcq - feat(lam, j + 8);
-#pragma unroll
-            for (int u = 0; u < EA; u += 2) {
-                const float a = frq - feat(lam, rb + (u >> 1));
-                const float a2 = a * a;
-                const float e0 = iqs - pv[u], e1 = iqs - pv[u + 1];
-                const uint32_t d0 = __float_as_uint(fmaf(e0, e0, fmaf(b0, b0, a2)));
-                const uint32_t d1 = __float_as_uint(fmaf(e1, e1, fmaf(b1, b1, a2)));
-                x[u] = d0;  // NaN bits for a query off the frame (segment unused)
-                x[u + 1] = d1;
-            }
+            if (lp == 0) S.iq[sq] = iqs;
+            seg_sort_pk<8, WAVE>(xp, lp);
+            // each group's element m - 1 (lane (m-1) / 8, register (m-1) % 8);
+            // at least K candidates lie at or below the larger key
+            const int m = (K + 1) / 2;
+            const uint32_t v = xp[uni((m - 1) % 8)];  // uniform register index
+            const uint32_t kk = max(v & 0xffffu, v >> 16);
+            if (lp == (m - 1) / 8) S.tauhi[sq] = sok ? kk << 16 : 0u;
         } else {
+            uint32_t x[EA];
+            float pv[EA];
+            // full blocks: lane lp takes block column offset jl (a permutation of
+            // 0..7), so that the columns of every group spread over the block
+            const int jl = NG * (lp % LG) + lp / LG;
+            if (EA == 8 && NA == WAVE && W >= 8 && !ballot(lbr != 3)) {
+                // every block is 8 x 8 (P = 8): element u * 8 + lp is row rb + u,
+                // column cb + jl < W, so a lane's column term is computed once
+                const int j = cb + jl;
+                const uint32_t o = (uint32_t)rb * (uint32_t)W + (uint32_t)j;
 #pragma unroll
-            for (int u = 0; u < EA; ++u) {
-                const int e = u * P + lp;
-                const int i = rb + (e >> lbc);
-                const int j = min(cb + (e & (bc - 1)), W - 1);
-                pv[u] = pc1[(uint32_t)i * (uint32_t)W + (uint32_t)j];
-            }
-#pragma unroll
-            for (int u = 0; u < EA; ++u) {
-                const int e = u * P + lp;
-                const int i = rb + (e >> lbc);
-                const int j = cb + (e & (bc - 1));
-                const float a = frq - feat(lam, i);
+                for (int u = 0; u < EA; ++u) pv[u] = pc1[o + (uint32_t)u * (uint32_t)W];
                 const float b = fcq - feat(lam, j);
-                const float ee = iqs - pv[u];
-                const uint32_t d = __float_as_uint(fmaf(ee, ee, fmaf(b, b, a * a)));
-                x[u] = (sok && j < W) ? d : 0x7f800000u;  // +inf: no candidate
+#pragma unroll
+                for (int u = 0; u < EA; ++u) {
+                    const float a = frq - feat(lam, rb + u);
+                    const float ee = iqs - pv[u];
+                    const uint32_t d = __float_as_uint(fmaf(ee, ee, fmaf(b, b, a * a)));
+                    x[u] = d;  // NaN bits for a query off the frame (segment unused)
+                }
+            } else if (EA == 16 && NA == 128 && W >= 16 && off32 && !ballot(lbr != 3)) {
+                // every block is 8 x 16 (P = 8): element u * 8 + lp is row
+                // rb + u / 2, column cb + 8 (u % 2) + jl < W, so a lane has two
+                // column terms and each row term serves two elements.  Byte
+                // offsets from the band's base fit 32 bits (off32): one add per
+                // row, the second column half as the load's immediate offset.
+                const int j = cb + jl;
+                const uint32_t o4 = ((uint32_t)rb * (uint32_t)W + (uint32_t)j) * 4u;
+                const char* __restrict__ pcb = (const char*)pc1;
+#pragma unroll
+                for (int u = 0; u < EA; ++u)
+                    pv[u] = *(const float*)(pcb + (o4 + (uint32_t)(u >> 1) * (uint32_t)W * 4u) +
+                                            32u * (u & 1));
+                const float b0 = fcq - feat(lam, j), b1 = fcq - feat(lam, j + 8);
+#pragma unroll
+                for (int u = 0; u < EA; u += 2) {
+                    const float a = frq - feat(lam, rb + (u >> 1));
+                    const float a2 = a * a;
+                    const float e0 = iqs - pv[u], e1 = iqs - pv[u + 1];
+                    const uint32_t d0 = __float_as_uint(fmaf(e0, e0, fmaf(b0, b0, a2)));
+                    const uint32_t d1 = __float_as_uint(fmaf(e1, e1, fmaf(b1, b1, a2)));
+                    x[u] = d0;  // NaN bits for a query off the frame (segment unused)
+                    x[u + 1] = d1;
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < EA; ++u) {
+                    const int e = u * P + lp;
+                    const int i = rb + (e >> lbc);
+                    const int j = min(cb + (e & (bc - 1)), W - 1);
+                    pv[u] = pc1[(uint32_t)i * (uint32_t)W + (uint32_t)j];
+                }
+#pragma unroll
+                for (int u = 0; u < EA; ++u) {
+                    const int e = u * P + lp;
+                    const int i = rb + (e >> lbc);
+                    const int j = cb + (e & (bc - 1));
+                    const float a = frq - feat(lam, i);
+                    const float b = fcq - feat(lam, j);
+                    const float ee = iqs - pv[u];
+                    const uint32_t d = __float_as_uint(fmaf(ee, ee, fmaf(b, b, a * a)));
+                    x[u] = (sok && j < W) ? d : 0x7f800000u;  // +inf: no candidate
+                }
             }
+            if (lp == 0) S.iq[sq] = iqs;
+            seg_sort_u32<EA, GS>(x, lp);
+            // each group's element m - 1 (group lane (m-1) / EA, register
+            // (m-1) % EA); the largest of the NG goes to the group-0 holder,
+            // which writes the bound
+            const int m = (K + NG - 1) / NG;
+            const int uk = uni((m - 1) % EA);
+            uint32_t dk = x[uk];  // uniform register index
+            if constexpr (NG > 1) {
+                dk = (lp % LG) == (m - 1) / EA ? dk : 0u;
+                if constexpr (LG == 2) dk = max(dk, xlane<2>(dk));
+                dk = max(dk, xlane<4>(dk));
+            }
+            if (lp == (m - 1) / EA) S.tauhi[sq] = sok ? dk : 0u;
         }
-        if (lp == 0) S.iq[sq] = iqs;
-        seg_sort_u32<EA, GS>(x, lp);
-        // each group's element m - 1 (group lane (m-1) / EA, register
-        // (m-1) % EA); the largest of the NG goes to the group-0 holder,
-        // which writes the bound
-        const int m = (K + NG - 1) / NG;
-        const int uk = uni((m - 1) % EA);
-        uint32_t dk = x[uk];  // uniform register index
-        if constexpr (NG > 1) {
-            dk = (lp % LG) == (m - 1) / EA ? dk : 0u;
-            if constexpr (LG == 2) dk = max(dk, xlane<2>(dk));
-            dk = max(dk, xlane<4>(dk));
-        }
-        if (lp == (m - 1) / EA) S.tauhi[sq] = sok ? dk : 0u;
         wave_sync();
     }
 
@@ -743,7 +891,7 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
             // lanes past the right edge get b = +inf, so every distance there is
             // +inf (never below a finite bound; the append step checks `valid`)
             float b[QC];
-    #pragma unroll
+#pragma unroll
             for (int qc = 0; qc < QC; ++qc) b[qc] = valid ? feat(lam, c0 + qc) - feat(lam, j) : pinf;
 
             const int lo = rlo, hi = rhi;
@@ -769,27 +917,27 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
                 const uint32_t joff = (uint32_t)jl;
                 const float* __restrict__ rowp = pc1 + (size_t)(blk + g0) * W;
                 float ipn[4];
-    #pragma unroll
+#pragma unroll
                 for (int u = 0; u < 4; ++u)
                     ipn[u] = rowp[(size_t)min(u, g1 - g0) * W + joff];
                 for (int g = g0; g <= g1; g += 4) {
                     float ip[4];
-    #pragma unroll
+#pragma unroll
                     for (int u = 0; u < 4; ++u) ip[u] = ipn[u];
                     if (g + 4 <= g1) {
                         const float* __restrict__ np = pc1 + (size_t)(blk + g + 4) * W;
-    #pragma unroll
+#pragma unroll
                         for (int u = 0; u < 4; ++u) ipn[u] = np[(size_t)min(u, g1 - g - 4) * W + joff];
                     }
                     float a2[4][QR];
-    #pragma unroll
+#pragma unroll
                     for (int u = 0; u < 4; ++u)
-    #pragma unroll
+#pragma unroll
                         for (int qr = 0; qr < QR; ++qr) a2[u][qr] = S.a2t[g + u][qr];
                     const int i0 = blk + g;
                     if (f.stats) {
                         const int nvl = min(WAVE, W - J);
-    #pragma unroll
+#pragma unroll
                         for (int qr = 0; qr < QR; ++qr) {
                             const int r = r0 + qr;
                             const int a = max(i0, max(lo, r - R)), z = min(i0 + 3, min(hi, r + R));
@@ -797,11 +945,11 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
                         }
                     }
                     uint32_t ovf = 0;  // queries whose buffer cannot take this group's survivors
-    #pragma unroll
+#pragma unroll
                     for (int q = 0; q < Q; ++q) {
                         const int qr = q / QC, qc = q % QC;
                         float d[4];
-    #pragma unroll
+#pragma unroll
                         for (int u = 0; u < 4; ++u) {
                             const float e = iq[q] - ip[u];
                             const float tt = fmaf(b[qc], b[qc], a2[u][qr]);
@@ -816,7 +964,7 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
                             bool rok[4];  // group rows inside the query row's window
                             uint64_t mu[4];
                             int n = 0;
-    #pragma unroll
+#pragma unroll
                             for (int u = 0; u < 4; ++u) {
                                 const int i = i0 + u;
                                 rok[u] = i <= hi && i >= r - R && i <= r + R;
@@ -824,7 +972,7 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
                                 n += __builtin_popcountll(mu[u]);
                             }
                             if (cnt[q] + n <= WAVE) {
-    #pragma unroll
+#pragma unroll
                                 for (int u = 0; u < 4; ++u) {
                                     if (valid && rok[u] && __float_as_uint(d[u]) <= th[q])
                                         S.pend[q][cnt[q] + mbcnt(mu[u])] = make_key(d[u], (i0 + u) * W + j);
@@ -838,7 +986,7 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
                     if (ovf) {
                         // rare: merge full buffers into the sorted lists (which
                         // tightens the bounds), appending the group row by row
-    #pragma unroll
+#pragma unroll
                         for (int q = 0; q < Q; ++q)
                             if (L == 0) S.cnt[q] = cnt[q];
                         wave_sync();
@@ -876,7 +1024,7 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
                             }
                             wave_sync();
                         }
-    #pragma unroll
+#pragma unroll
                         for (int q = 0; q < Q; ++q) {
                             cnt[q] = uni(S.cnt[q]);
                             th[q] = S.tauhi[q];
