@@ -23,9 +23,13 @@
 //   * pass A (bound): the 128 candidates (8-query tiles; 64 for 16-query
 //     tiles) of a compact block around each query (8 rows x 16 columns where
 //     the window allows) are evaluated and sorted for all Q queries at once
-//     by a segmented bitonic network; the K-th distance d_K bounds the
-//     query's final K-th key from above.  The larger block's tighter bound
-//     lets fewer candidates through the scan than an 8 x 8 block's.
+//     by a segmented bitonic network; any distance with at least K block
+//     candidates at or below it bounds the query's final K-th key from
+//     above.  8-query tiles sort the block as two interleaved groups of 64
+//     (16-bit keys rounded up, both groups in one packed network) and take
+//     the larger of the groups' ceil(K/2)-th keys; other tiles take the
+//     block's K-th distance.  The larger block's tighter bound lets fewer
+//     candidates through the scan than an 8 x 8 block's.
 //   * pass B (collect): candidates with d <= d_K are appended to a per-query
 //     LDS buffer with ballot + mbcnt; a full buffer is merged into a sorted
 //     per-query list, which tightens the bound.  Two scans:
