@@ -1147,9 +1147,12 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
     const uint32_t rowb = (uint32_t)C * 4u;  // bytes per probability row
     const uint64_t npix = (uint64_t)H * (uint64_t)W;
     const bool off24 = npix <= (1u << 24) && npix * rowb <= 0xFFFFFFFFull;
+    // p / C by a reciprocal: (p + 0.5) / C sits at least 1/(2C) >= 1/32 from
+    // an integer and p < 2^10, far beyond the reciprocal's rounding
+    const float rc = __builtin_amdgcn_rcpf((float)C);
     for (int p = L; p < Q * C; p += WAVE) {
-        const int q = p / C, cl = p - q * C;
-        const int qr = q / QC, qc = q % QC;
+        const int q = (int)(uint32_t)(((float)p + 0.5f) * rc), cl = p - q * C;
+        const int qr = (int)((uint32_t)q / QC), qc = (int)((uint32_t)q % QC);
         if (qr >= nqr || qc >= nqc) continue;
         const uint32_t* lst = S.list[q];
         float s = 0.0f;
@@ -1173,8 +1176,14 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
             for (; k < K; ++k) s = s + *(const float*)(pb + (uint64_t)lst[k] * rowb);
         }
         S.sums[q][cl] = s;
-        const size_t pix = (size_t)(r0 + qr) * W + c0 + qc;
-        f.out_prob[pix * C + cl] = s / (float)K;
+        if (off24) {
+            // the pixel's byte offset in the probability map fits 32 bits
+            const uint32_t pix = (uint32_t)(r0 * W + c0) + __umul24((uint32_t)qr, (uint32_t)W) + (uint32_t)qc;
+            *(float*)((char*)f.out_prob + (__umul24(pix, rowb) + (uint32_t)cl * 4u)) = s / (float)K;
+        } else {
+            const size_t pix = (size_t)(r0 + qr) * W + c0 + qc;
+            f.out_prob[pix * C + cl] = s / (float)K;
+        }
     }
     wave_sync();
     if (L < Q) {
@@ -1186,7 +1195,10 @@ __device__ __forceinline__ void process_tile(TileLds<QR, QC, PRUNE>& S, const Fr
                 const float v = S.sums[L][cl];
                 if (v > bs) { bs = v; best = cl; }
             }
-            f.out_class[(size_t)(r0 + qr) * W + c0 + qc] = best;
+            if (off24)
+                f.out_class[(uint32_t)(r0 * W + c0) + __umul24((uint32_t)qr, (uint32_t)W) + (uint32_t)qc] = best;
+            else
+                f.out_class[(size_t)(r0 + qr) * W + c0 + qc] = best;
         }
     }
     if (f.stats && L == 0) {
