@@ -320,6 +320,27 @@ def test_unwindowed_whole_frame(ctx):
         assert_parity(run_gpu(ctx, pc1, prob, 40, 500, 0.01, plan), ref, "unwindowed")
 
 
+def test_frame_past_24_bit_indices_sampled(ctx):
+    """W 4100 x H 4100 (16.81 M pixels, past 2^24): the linear indices no
+    longer fit the 24-bit multiply-adds of the Eq. 2 gathers and output
+    stores, so their 64-bit address paths run.  Default pruned plan; the
+    first and last 64 pixels and 200 random ones against the oracle."""
+    H = W = 4100
+    K, R, lam = 8, 2, 0.01
+    assert H * W > 1 << 24
+    pc1, prob = inputs.g_unif(H, W, 41)
+    say("past 2^24 pixels")
+    go, gc, gn, gd = run_gpu(ctx, pc1, prob, K, R, lam, PRU18)
+    rng = np.random.default_rng(41)
+    pix = np.concatenate([np.arange(64), np.arange(H * W - 64, H * W),
+                          rng.choice(H * W, 200, replace=False)])
+    ro, rc, rn, rd = oracle.knn_pixels(pc1, prob, K, R, lam, pix)
+    assert np.array_equal(gn.reshape(H * W, K)[pix], rn)
+    assert np.array_equal(gd.reshape(H * W, K)[pix].view(np.uint32), rd.view(np.uint32))
+    assert np.array_equal(gc.reshape(-1)[pix], rc)
+    assert float(np.max(np.abs(go.reshape(H * W, -1)[pix].astype(np.float64) - ro))) <= PROB_TOL
+
+
 def test_unwindowed_full_size_sampled(ctx):
     """W 480 x H 380, K = 40, whole-frame window, pruned search: 300 sampled
     pixels against the oracle (182,400 candidates each)."""
